@@ -1,0 +1,375 @@
+"""Pins of the oracle's messenger iteration.
+
+Each pin checks the oracle against something other than its own formulas:
+the exact minimiser of a dense joint quadratic, a dense Cholesky solve, a
+Fourier closed form, the chi^2 gradient, or an invariant of the method.
+"""
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from oracle import bases, direct
+from oracle.messenger import State
+
+
+# --------------------------------------------------------------------------
+# helpers: dense matrices built from the problem definition
+# --------------------------------------------------------------------------
+
+def _tiny_problem(mask=True, seed=5):
+    p = synth.make_problem(8, 8, seed, pix_arcmin=20.0)
+    if mask:
+        m = np.ones((8, 8), np.uint8)
+        m[2:4, 3:6] = 0
+        m[6, 0] = 0
+        p.mask = m
+    return p
+
+
+def _dense_chain(p, settings, lam):
+    """Covariances along the chain, signal end first, as dense matrices:
+    [S_chain, T_0, Nbar_0, T_1, Nbar_1, ...], built from the problem arrays
+    with tau_i recomputed from eigenvalues of the dense noise terms."""
+    ny, nx = p.d.shape
+    n = ny * nx
+    I = np.eye(n)
+    obs = np.ones(n, bool) if p.mask is None else p.mask.ravel() != 0
+    b0, b1, b2 = settings.beta
+    S = direct.stationary_cov_dense(p.s_k, nx)
+    Noof = direct.stationary_cov_dense(p.p_oof, nx)
+    Nst = direct.stripe_cov_dense(p.p_stripe, nx)
+    npix = p.n_pix.ravel()
+    covs, nbar_pix = [], None
+    if settings.chain == "three":
+        phi = settings.floor_frac * npix[obs].min()
+        N1 = Nst + phi * I
+        tau0 = b0 * np.linalg.eigvalsh(Noof).min()
+        tau1 = b1 * np.linalg.eigvalsh(N1).min()
+        tau2 = b2 * (npix - phi)[obs].min()
+        covs = [S, lam * tau0 * I, Noof - tau0 * I, lam * tau1 * I, N1 - tau1 * I,
+                lam * tau2 * I]
+        nbar_pix = npix - phi - tau2
+    elif settings.chain == "merged":
+        NF = Noof + Nst
+        tau0 = b0 * np.linalg.eigvalsh(NF).min()
+        tau2 = b2 * npix[obs].min()
+        covs = [S, lam * tau0 * I, NF - tau0 * I, lam * tau2 * I]
+        nbar_pix = npix - tau2
+    else:
+        tau2 = b2 * npix[obs].min()
+        covs = [S + Noof + Nst, lam * tau2 * I]
+        nbar_pix = npix - tau2
+    return covs, nbar_pix, obs
+
+
+def _joint_hessian(covs, nbar_pix, obs, d):
+    """J = z^T H z - 2 b^T z + const for fields z = (s, t_0, d_0, ..., t_last)
+    linked by the chain covariances, the last one tied to the data d."""
+    n = d.size
+    nf = len(covs)
+    H = np.zeros((nf * n, nf * n))
+    b = np.zeros(nf * n)
+
+    def blk(i):
+        return slice(i * n, (i + 1) * n)
+
+    H[blk(0), blk(0)] += np.linalg.inv(covs[0])
+    for i in range(1, nf):
+        M = np.linalg.inv(covs[i])
+        H[blk(i - 1), blk(i - 1)] += M
+        H[blk(i), blk(i)] += M
+        H[blk(i - 1), blk(i)] -= M
+        H[blk(i), blk(i - 1)] -= M
+    winv = np.where(obs, 1.0 / np.where(obs, nbar_pix, 1.0), 0.0)
+    H[blk(nf - 1), blk(nf - 1)] += np.diag(winv)
+    b[blk(nf - 1)] += winv * d.ravel()
+    return H, b, blk
+
+
+def _fields(x):
+    out = [x.s]
+    for i in range(len(x.t)):
+        out.append(x.t[i])
+        if i < len(x.dd):
+            out.append(x.dd[i])
+    return out
+
+
+def _vec(x):
+    return np.concatenate([f.ravel() for f in _fields(x)])
+
+
+# --------------------------------------------------------------------------
+# every single update is the exact conditional minimiser (eqn 2mess_prob)
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("chain", ["three", "merged", "augmented"])
+@pytest.mark.parametrize("lam", [1.0, 7.0])
+def test_each_update_is_exact_conditional_minimiser(chain, lam):
+    p = _tiny_problem()
+    settings = oracle.Settings(beta=(0.8, 0.7, 0.9), floor_frac=0.5, chain=chain)
+    st = oracle.setup(p, settings)
+    covs, nbar_pix, obs = _dense_chain(p, settings, lam)
+    H, b, blk = _joint_hessian(covs, nbar_pix, obs, p.d)
+    m = len(st.levels)
+    rng = np.random.default_rng(0)
+    x = State(t=[30 * rng.standard_normal(p.d.shape) for _ in range(m)],
+              dd=[30 * rng.standard_normal(p.d.shape) for _ in range(m - 1)],
+              s=30 * rng.standard_normal(p.d.shape))
+    # position of each named field in the chain vector
+    pos = {"s": 0}
+    for i in range(m):
+        pos[f"t{i}"] = 2 * i + 1
+        pos[f"d{i}"] = 2 * i + 2
+    nf = len(covs)
+    prev = [_vec(x)]
+    seen = []
+
+    def check(name):
+        z0, z1 = prev[0], _vec(x)
+        i = pos[name]
+        rest = b[blk(i)] - sum(H[blk(i), blk(j)] @ z0[blk(j)] for j in range(nf) if j != i)
+        expect = np.linalg.solve(H[blk(i), blk(i)], rest)
+        got = z1[blk(i)]
+        assert np.linalg.norm(got - expect) <= 1e-11 * np.linalg.norm(expect), name
+        others = np.delete(z1 - z0, np.r_[blk(i)])
+        assert np.all(others == 0.0), name
+        seen.append(name)
+        prev[0] = z1
+
+    oracle.sweep(st, x, lam, on_update=check)
+    expected_order = {"three": ["t2", "d1", "t1", "d0", "t0", "s"],
+                      "merged": ["t1", "d0", "t0", "s"],
+                      "augmented": ["t0", "s"]}[chain]
+    assert seen == expected_order
+
+
+# --------------------------------------------------------------------------
+# the fixed point is the Wiener filter
+# --------------------------------------------------------------------------
+
+def _easy_three_term(seed=7, mask=False):
+    p = synth.make_problem(32, 32, seed, pix_arcmin=4.0, stripe_rms=3.0,
+                           white_contrast=0.2)
+    if mask:
+        m = np.ones((32, 32), np.uint8)
+        yy, xx = np.mgrid[:32, :32]
+        m[(yy - 10) ** 2 + (xx - 20) ** 2 <= 16] = 0
+        p.mask = m
+    return p
+
+
+def test_three_level_chain_converges_to_dense_cholesky():
+    """Unmasked: with a mask the three-level chain needs far more sweeps than a
+    unit test affords (masked regions are the slowest, Section 3.2); the masked
+    fixed point is pinned through the variant chains below."""
+    p = _easy_three_term(mask=False)
+    sd = direct.wiener_dense(p)
+    r = oracle.solve(p, oracle.AdaptiveSchedule(lam0=1e3, plateau=1e-3),
+                     max_sweeps=30000, monitor_every=4, rtol=1e-11)
+    assert r.converged
+    assert np.linalg.norm(r.s - sd) / np.linalg.norm(sd) < 1e-9
+
+
+@pytest.mark.parametrize("chain,mask", [("augmented", True), ("augmented", False),
+                                        ("merged", False)])
+def test_variant_chains_share_the_fixed_point(chain, mask):
+    """Appendix A shortcuts keep the Wiener fixed point.  (The merged chain
+    with a mask needs more sweeps than a unit test affords.)"""
+    p = _easy_three_term(mask=mask)
+    sd = direct.wiener_dense(p)
+    r = oracle.solve(p, oracle.AdaptiveSchedule(lam0=1e3, plateau=1e-3),
+                     settings=oracle.Settings(chain=chain),
+                     max_sweeps=40000, monitor_every=4, rtol=1e-12, full_residual=True)
+    assert r.converged
+    assert np.linalg.norm(r.s - sd) / np.linalg.norm(sd) < 1e-9
+
+
+def test_c1_augmented_chain_matches_dense_cholesky():
+    """The 64x64 three-term workload against the 4096x4096 Cholesky solve."""
+    p = synth.named_config("c1")
+    sd = direct.wiener_dense(p)
+    r = oracle.solve(p, oracle.AdaptiveSchedule(lam0=1e4, plateau=1e-2),
+                     settings=oracle.Settings(chain="augmented"),
+                     max_sweeps=5000, monitor_every=1, rtol=1e-12)
+    assert r.converged
+    assert np.linalg.norm(r.s - sd) / np.linalg.norm(sd) < 1e-10
+
+
+def test_stationary_closed_form_three_levels():
+    """No mask, uniform white noise: N is Fourier diagonal and the Wiener
+    filter is a per-mode ratio; the stripe term sits on k_x = 0 there, while
+    the iteration applies it through row means."""
+    p = synth.make_stationary_problem(32, 32, 11, pix_arcmin=4.0, stripe_rms=3.0)
+    sc = direct.wiener_stationary(p)
+    np.testing.assert_allclose(sc, direct.wiener_dense(p), rtol=0, atol=1e-10 * np.abs(sc).max())
+    r = oracle.solve(p, oracle.AdaptiveSchedule(lam0=1e3, plateau=1e-3),
+                     max_sweeps=30000, monitor_every=4, rtol=1e-12)
+    assert r.converged
+    assert np.linalg.norm(r.s - sc) / np.linalg.norm(sc) < 1e-10
+
+
+def test_ew_limit_converges_in_one_sweep():
+    """Section 3.1: with only uniform white noise and tau = sigma^2 the
+    messenger takes all of the noise and one sweep gives the exact filter."""
+    p = synth.make_stationary_problem(64, 64, 3, oof_level=None, stripe_rms=None)
+    settings = oracle.Settings(beta=(0.9, 0.9, 1.0))
+    st = oracle.setup(p, settings)
+    x = oracle.init_state(st, 1.0)
+    oracle.sweep(st, x, 1.0)
+    sigma2 = p.n_pix[0, 0]
+    dk = np.fft.rfft2(p.d)
+    expect = np.fft.irfft2(p.s_k / (p.s_k + sigma2) * dk, s=p.d.shape)
+    np.testing.assert_allclose(x.s, expect, rtol=0, atol=1e-13 * np.abs(expect).max())
+
+
+# --------------------------------------------------------------------------
+# invariants
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("chain", ["three", "merged"])
+def test_joint_objective_never_increases(chain):
+    """Appendix A: every update maximises P_2 along one field, so J_lambda
+    cannot go up after any single-field update at fixed lambda."""
+    p = _easy_three_term(mask=True)
+    settings = oracle.Settings(beta=(0.9, 0.9, 0.95), chain=chain)
+    st = oracle.setup(p, settings)
+    x = oracle.init_state(st, 5.0)
+    for lam in [50.0, 5.0, 1.0]:
+        js = [oracle.joint_objective(st, x, lam)]
+
+        def cb(_name):
+            js.append(oracle.joint_objective(st, x, lam))
+        for _ in range(5):
+            oracle.sweep(st, x, lam, on_update=cb)
+        steps = np.diff(js)
+        assert np.all(steps <= 1e-12 * abs(js[0])), steps.max()
+
+
+def test_residual_is_noise_times_half_chi2_gradient():
+    """N grad(chi^2)/2 = (I + N S^-1) s - d = Delta d for any s (Sections 1
+    and 2, no mask), checked with dense N at an arbitrary state."""
+    p = _easy_three_term(mask=False)
+    st = oracle.setup(p)
+    x = oracle.init_state(st, 1.0)
+    for _ in range(3):
+        oracle.sweep(st, x, 3.0)
+    lam = 3.0
+    dg = oracle.diagnostics(st, x, lam)
+    s = oracle.messenger.final_signal(st, x, lam)
+    _, N = direct.dense_covariances(p)
+    g = direct.grad_chi2_dense(p, s)
+    dd = N @ (0.5 * g.ravel())
+    assert np.sqrt(np.sum(dd ** 2)) == pytest.approx(np.sqrt(dg.dd2), rel=1e-9)
+    assert dg.rho == pytest.approx(np.linalg.norm(dd) / np.linalg.norm(p.d), rel=1e-9)
+
+
+def test_converged_solution_is_stationary_and_profile_identity_holds():
+    """At convergence grad chi^2 = 0, and min over messengers of J_1 equals
+    chi^2(s) (marginalising the messengers returns P(s, d), Appendix A)."""
+    p = _easy_three_term(mask=False)
+    r = oracle.solve(p, oracle.AdaptiveSchedule(lam0=1e3, plateau=1e-3),
+                     max_sweeps=30000, monitor_every=4, rtol=1e-12)
+    assert r.converged
+    g = direct.grad_chi2_dense(p, r.s)
+    sk = np.fft.fft2(r.s, norm="ortho")
+    prior_grad_scale = np.linalg.norm(
+        np.fft.ifft2(sk / bases.full_from_half(p.s_k, 32), norm="ortho").real)
+    assert np.linalg.norm(g) < 1e-8 * prior_grad_scale
+    st = oracle.setup(p)
+    J = oracle.joint_objective(st, r.state, 1.0)
+    assert J == pytest.approx(direct.chi2_dense(p, r.s), rel=1e-9)
+
+
+def test_unit_beta_on_inner_level_locks_modes():
+    """tau_1 equal to the smallest stripe-level eigenvalue makes Nbar_1 zero
+    off the row-constant modes: d_1 and t_1 then copy each other and those
+    components never leave their start."""
+    p = _easy_three_term()
+    st = oracle.setup(p, oracle.Settings(beta=(0.9, 1.0, 1.0)))
+    x = oracle.init_state(st, 1.0)
+    for _ in range(20):
+        oracle.sweep(st, x, 10.0)
+    t1 = x.t[1]
+    off_rows = t1 - t1.mean(axis=1, keepdims=True)
+    assert np.max(np.abs(off_rows)) == 0.0
+    assert np.max(np.abs(t1)) > 0.0  # the row-constant part did move
+
+
+def test_cooling_beats_no_cooling():
+    """Section 3.3: without cooling the iteration is much slower."""
+    p = _easy_three_term(mask=True)
+    kw = dict(settings=oracle.Settings(chain="augmented"), max_sweeps=3000,
+              monitor_every=1, rtol=1e-6)
+    cooled = oracle.solve(p, oracle.AdaptiveSchedule(lam0=1e3), **kw)
+    flat = oracle.solve(p, oracle.FixedSchedule([1.0]), **kw)
+    assert cooled.converged
+    assert (not flat.converged) or flat.sweeps > cooled.sweeps
+
+
+def test_more_noise_in_fourier_level_converges_faster():
+    """Section 3.1: uniform white noise split between a harmonic term and a
+    pixel term converges faster the more of it sits in the harmonic term."""
+    sweeps = {}
+    for frac in (0.99, 0.5):
+        p = synth.make_stationary_problem(32, 32, 4, oof_level=None, stripe_rms=None)
+        sigma2 = p.n_pix[0, 0]
+        p.p_oof = np.full_like(p.s_k, frac * sigma2)
+        p.n_pix = np.full_like(p.n_pix, (1 - frac) * sigma2)
+        r = oracle.solve(p, oracle.FixedSchedule([1.0]),
+                         settings=oracle.Settings(beta=(0.5, 0.9, 0.5)),
+                         max_sweeps=5000, monitor_every=1, rtol=1e-6)
+        assert r.converged
+        sweeps[frac] = r.sweeps
+    assert sweeps[0.99] < sweeps[0.5]
+
+
+def test_convergence_is_exponential_at_unit_lambda():
+    """Section 3.2: once the fast modes have died out the log residual falls
+    linearly with the sweep count."""
+    p = _easy_three_term(mask=True)
+    r = oracle.solve(p, oracle.FixedSchedule([1.0]),
+                     settings=oracle.Settings(chain="augmented"),
+                     max_sweeps=2000, monitor_every=1)
+    rho = np.array([np.hypot(t[2], t[4]) for t in r.trace])
+    late = np.log(rho[1200:2000])
+    k = np.arange(late.size)
+    slope, icpt = np.polyfit(k, late, 1)
+    assert slope < 0
+    assert np.max(np.abs(late - (slope * k + icpt))) < 0.02 * abs(late[0] - late[-1])
+
+
+# --------------------------------------------------------------------------
+# error conditions (Section 3.1: an empty covariance makes the method fail)
+# --------------------------------------------------------------------------
+
+def test_empty_noise_term_is_not_positive_definite():
+    p = _easy_three_term()
+    p.p_oof = np.zeros_like(p.p_oof)
+    with pytest.raises(oracle.NotPositiveDefinite):
+        oracle.setup(p)
+
+
+def test_stripe_level_without_floor_is_not_positive_definite():
+    p = _easy_three_term()
+    with pytest.raises(oracle.NotPositiveDefinite):
+        oracle.setup(p, oracle.Settings(floor_frac=0.0))
+
+
+def test_all_masked_is_invalid():
+    p = _easy_three_term()
+    p.mask = np.zeros_like(p.d, dtype=np.uint8)
+    with pytest.raises(oracle.InvalidInput):
+        oracle.setup(p)
+
+
+def test_masked_pixels_are_ignored():
+    p = _easy_three_term(mask=True)
+    r1 = oracle.solve(p, oracle.FixedSchedule(oracle.cooling_ramp(20, 40, 1e3)), max_sweeps=40)
+    q = _easy_three_term(mask=True)
+    q.d = np.where(q.mask == 0, 1e6, q.d)
+    q.n_pix = np.where(q.mask == 0, -5.0, q.n_pix)
+    r2 = oracle.solve(q, oracle.FixedSchedule(oracle.cooling_ramp(20, 40, 1e3)), max_sweeps=40)
+    np.testing.assert_array_equal(r1.s, r2.s)
