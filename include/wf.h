@@ -1,0 +1,162 @@
+/*
+ * wf.h -- multi-messenger Wiener filter on one AMD MI355X (gfx950).
+ *
+ * Computes the Wiener filter s = S (S + N)^-1 d (eqn wiener-alt of
+ * Huffenberger 2017) of a periodic flat-sky map d whose noise covariance is
+ * dense but splits into parts that are each diagonal in some basis
+ * (Section 2):
+ *     N = N_1/f   (diagonal in the 2-D Fourier basis)
+ *       + N_stripe (noise constant along each row, diagonal in the basis of
+ *                   row-constant Fourier modes; Section 3.3's m = 0 stripes)
+ *       + N_white (diagonal in pixel space; infinite on masked pixels)
+ * by iterating the messenger-field equations (eqns ew_t/ew_s, 2mess_t1 to
+ * 2mess_s, extended by one messenger per extra term) with the cooling of
+ * Section 2 and the adaptive schedule of Section 3.3.
+ *
+ * Conventions shared by every call:
+ *   - a map is ny x nx, row-major (x fastest), periodic;
+ *   - a Fourier-diagonal covariance is given on the rfft2 half spectrum,
+ *     [ny][nx/2+1] row-major, as the variance of each *unitary* 2-D DFT mode
+ *     in pixel-variance units (a spectrum C(l) maps to C(l)/Omega_pix, the
+ *     correspondence N = (sigma^2/Omega_pix) I <-> N_l = sigma^2 of Section
+ *     3.1); it must satisfy v(-ky, 0) = v(ky, 0) (likewise at kx = nx/2) as
+ *     the covariance of a real field does;
+ *   - the stripe covariance is the variance of each unitary 1-D DFT mode of
+ *     the row value f(y), [ny] in FFT order (stripe map n(x, y) = f(y));
+ *   - sizes: nx, ny powers of two in [64, 4096] (FP64 path: up to 2048);
+ *   - every pointer in wf_inputs, s_init and s_out is a DEVICE pointer owned
+ *     by the caller; arrays are float (WF_F32) or double (WF_F64) as the
+ *     context's precision says; the mask is uint8 (1 observed, 0 masked);
+ *   - calls are ordered on the given HIP stream and return after their last
+ *     device-to-host readback; one context per host thread at a time.
+ * Errors: a negative status leaves outputs untouched; WF_NOT_CONVERGED means
+ * the sweep budget ran out and every output is valid.
+ */
+#ifndef WF_H
+#define WF_H
+
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  WF_OK = 0,
+  WF_NOT_CONVERGED = 1,   /* budget exhausted; s_out and the report are valid */
+  WF_EINVAL = -1,         /* bad shape, pointer or option                        */
+  WF_ENOTPD = -2,         /* some tau_i <= 0: an empty noise term (Section 3.1)  */
+  WF_ENONFINITE = -3,     /* NaN/Inf in the inputs or in the iteration           */
+  WF_EDEVICE = -4,        /* a HIP call failed                                   */
+  WF_ENOMEM = -5,         /* device allocation failed                            */
+  WF_EUNSUPPORTED = -6    /* size/precision not built                            */
+} wf_status;
+
+typedef enum { WF_F32 = 0, WF_F64 = 1 } wf_precision;
+
+/* Which chain of messenger fields runs (all have the Wiener filter as fixed
+ * point at lambda = 1):
+ *  THREE     one level per noise term, signal side first: 1/f (2-D Fourier),
+ *            stripe (row basis), white (pixel) -- Section 2 extended to three
+ *            terms; a white floor phi = floor_frac * min(N_white) is moved to
+ *            the stripe level, whose own smallest eigenvalue is zero;
+ *  MERGED    1/f and stripes form one 2-D Fourier-diagonal term (stripes on
+ *            the k_x = 0 column), the arrangement of Section 3.3;
+ *  AUGMENTED every Fourier-diagonal noise term joins the signal,
+ *            S' = S + N_1/f + N_stripe, one messenger carries the white noise
+ *            and s = S S'^-1 u -- Appendix A's shortcut for terms that share
+ *            the signal's basis.  Fastest to converge. */
+typedef enum { WF_CHAIN_THREE = 0, WF_CHAIN_MERGED = 1, WF_CHAIN_AUGMENTED = 2 } wf_chain;
+
+typedef enum { WF_SCHED_FIXED = 0, WF_SCHED_ADAPTIVE = 1 } wf_sched_kind;
+
+typedef struct {
+  int32_t ny, nx;        /* map size                                   */
+  int32_t precision;     /* wf_precision of inputs, fields and output  */
+} wf_shape;
+
+typedef struct {         /* DEVICE pointers, caller-owned, read-only during the call */
+  const void* d;         /* [ny*nx] data                                          */
+  const void* s_k;       /* [ny*(nx/2+1)] signal mode variance, >= 0              */
+  const void* n_pix;     /* [ny*nx] white variance, > 0 on observed pixels        */
+  const void* p_oof;     /* [ny*(nx/2+1)] 1/f mode variance >= 0, or NULL (absent)*/
+  const void* p_stripe;  /* [ny] stripe 1-D mode variance >= 0, or NULL (absent)  */
+  const uint8_t* mask;   /* [ny*nx] 1 observed / 0 masked, or NULL (all observed) */
+} wf_inputs;
+
+typedef struct {         /* HOST struct */
+  int32_t kind;          /* wf_sched_kind                                               */
+  const double* lambda;  /* FIXED: lambda for sweep k is lambda[min(k, n_lambda-1)]     */
+  int32_t n_lambda;
+  double lambda0;        /* ADAPTIVE (Section 3.3): start value, e.g. 1e4               */
+  double shrink_exp;     /*   lambda <- lambda^shrink_exp on a plateau, e.g. 0.7        */
+  double plateau_rtol;   /*   plateau: |change of dd2| < plateau_rtol * sweeps * dd2    */
+  double snap_eps;       /*   lambda is set to 1 once lambda - 1 < snap_eps             */
+  double rtol;           /* stop when lambda == 1 and rho <= rtol (0: never)            */
+  int32_t max_sweeps;    /* sweep budget (>= 1)                                         */
+  int32_t monitor_every; /* residual evaluated every K sweeps and after the last one    */
+  double beta[3];        /* tau_i = beta_i * smallest eigenvalue of N_i (1/f, stripe,   */
+                         /*   white); beta < 1 where both chain neighbours are free     */
+  double floor_frac;     /* alpha: white floor lent to the stripe level                 */
+  int32_t chain;         /* wf_chain                                                    */
+  int32_t stop_full;     /* 1: stop test uses hypot(rho, rho_mask) instead of rho       */
+} wf_schedule;
+
+typedef struct {         /* HOST struct filled by wf_solve */
+  int32_t status;        /* same as the return value                                    */
+  int32_t sweeps;        /* sweeps executed                                             */
+  int32_t n_records;     /* monitor records written to the trace                        */
+  int32_t n_levels;      /* messenger levels in the chain                               */
+  double lambda;         /* lambda of the last sweep                                    */
+  double rho;            /* |m (d_rec - d)| / |m d|, d_rec = (I + N S^-1) s (Section 2) */
+  double rho_mask;       /* nu |(1-m) S^-1 s| / |m d|, nu = max observed white variance */
+  double dd2;            /* sum over observed pixels of (d_rec - d)^2                   */
+  double d2;             /* sum over observed pixels of d^2                             */
+  double tau[3];         /* messenger variances (1/f or merged, stripe, white); 0 absent*/
+  double phi;            /* white floor moved to the stripe level                       */
+  double kernel_ms[4];   /* profiling (wf_ctx_set_profiling): summed durations of the   */
+  int32_t kernel_launches[4]; /* row, column, monitor and controller kernels timed     */
+} wf_report;
+
+/* Create a context (device workspace, FFT tables) for one map shape on the
+ * current HIP device.  *out receives the handle; free with wf_ctx_destroy. */
+wf_status wf_ctx_create(const wf_shape* shape, void** out);
+void wf_ctx_destroy(void* ctx);
+
+/* Fill sch with the defaults: adaptive, lambda0 1e4, shrink 0.7, plateau 1e-2,
+ * snap 1e-3, rtol 1e-6, max_sweeps 20000, monitor_every 16,
+ * beta {0.9, 0.9, 1.0}, floor_frac 0.5, chain THREE. */
+void wf_schedule_default(wf_schedule* sch);
+
+/* Solve.  s_init: DEVICE [ny*nx] warm start (every messenger and data-like
+ * field starts at s_init, Section 2 notes the start is not critical), or NULL
+ * for the zero start of Section 2.  s_out: DEVICE [ny*nx].  rep: HOST, may be
+ * NULL.  trace: HOST [5 * ceil(max_sweeps / monitor_every)] rows of
+ * (sweep index, lambda, rho, dd2, rho_mask), or NULL. */
+wf_status wf_solve(void* ctx, const wf_inputs* in, const wf_schedule* sch,
+                   const void* s_init, void* s_out, wf_report* rep,
+                   double* trace, hipStream_t stream);
+
+/* Unnormalised 2-D real-to-complex FFT with the solver's own kernels:
+ * x [ny*nx] real -> X [ny*(nx/2+1)] complex (interleaved re, im), numpy rfft2
+ * layout and sign (X_k = sum_p x_p exp(-2 pi i k.p/n)).  DEVICE pointers. */
+wf_status wf_rfft2(void* ctx, const void* x, void* X, hipStream_t stream);
+
+/* Inverse of wf_rfft2 including the 1/(nx ny) factor, with numpy irfft2's
+ * semantics: inverse FFT over ky, then a real inverse FFT over kx that
+ * ignores the imaginary parts of the k_x = 0 and k_x = nx/2 bins. */
+wf_status wf_irfft2(void* ctx, const void* X, void* x, hipStream_t stream);
+
+/* Turn per-kernel timing with HIP events on the solve stream on (1) or off. */
+wf_status wf_ctx_set_profiling(void* ctx, int32_t enable);
+
+/* Sizes the library was built for, and its precision support. */
+int32_t wf_supported(int32_t ny, int32_t nx, int32_t precision);
+
+const char* wf_strerror(int32_t status);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* WF_H */

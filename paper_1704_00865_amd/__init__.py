@@ -1,0 +1,301 @@
+"""Multi-messenger Wiener filter on AMD MI355X (gfx950): Python binding.
+
+A thin ctypes layer over ``libwf.so`` (C ABI in ``include/wf.h``).  Every
+step of the filter runs in the library's HIP kernels; this module only
+checks tensor shapes and dtypes and passes device pointers and the current
+HIP stream.  PyTorch provides device memory and streams.  There is no
+fallback: if the library is missing, ``load()`` raises.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+from typing import Optional, Sequence
+
+import numpy as np
+
+__all__ = [
+    "load", "Context", "Schedule", "solve", "rfft2", "irfft2", "strerror",
+    "WFError", "STATUS", "CHAINS",
+]
+
+_LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libwf.so")
+_lib = None
+
+STATUS = {0: "OK", 1: "NOT_CONVERGED", -1: "EINVAL", -2: "ENOTPD", -3: "ENONFINITE",
+          -4: "EDEVICE", -5: "ENOMEM", -6: "EUNSUPPORTED"}
+CHAINS = {"three": 0, "merged": 1, "augmented": 2}
+
+
+class WFError(RuntimeError):
+    def __init__(self, status: int, what: str = ""):
+        self.status = status
+        super().__init__(f"{what}: {STATUS.get(status, status)} ({strerror(status)})")
+
+
+class _Shape(ctypes.Structure):
+    _fields_ = [("ny", ctypes.c_int32), ("nx", ctypes.c_int32), ("precision", ctypes.c_int32)]
+
+
+class _Inputs(ctypes.Structure):
+    _fields_ = [("d", ctypes.c_void_p), ("s_k", ctypes.c_void_p), ("n_pix", ctypes.c_void_p),
+                ("p_oof", ctypes.c_void_p), ("p_stripe", ctypes.c_void_p),
+                ("mask", ctypes.c_void_p)]
+
+
+class _Schedule(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("lam", ctypes.POINTER(ctypes.c_double)),
+                ("n_lambda", ctypes.c_int32), ("lambda0", ctypes.c_double),
+                ("shrink_exp", ctypes.c_double), ("plateau_rtol", ctypes.c_double),
+                ("snap_eps", ctypes.c_double), ("rtol", ctypes.c_double),
+                ("max_sweeps", ctypes.c_int32), ("monitor_every", ctypes.c_int32),
+                ("beta", ctypes.c_double * 3), ("floor_frac", ctypes.c_double),
+                ("chain", ctypes.c_int32), ("stop_full", ctypes.c_int32)]
+
+
+class _Report(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int32), ("sweeps", ctypes.c_int32),
+                ("n_records", ctypes.c_int32), ("n_levels", ctypes.c_int32),
+                ("lam", ctypes.c_double), ("rho", ctypes.c_double),
+                ("rho_mask", ctypes.c_double), ("dd2", ctypes.c_double),
+                ("d2", ctypes.c_double), ("tau", ctypes.c_double * 3),
+                ("phi", ctypes.c_double), ("kernel_ms", ctypes.c_double * 4),
+                ("kernel_launches", ctypes.c_int32 * 4)]
+
+
+EXPORTS = ("wf_ctx_create", "wf_ctx_destroy", "wf_schedule_default", "wf_solve", "wf_rfft2",
+           "wf_irfft2", "wf_ctx_set_profiling", "wf_supported", "wf_strerror")
+
+
+def load():
+    """Load libwf.so (built by ``paper_1704_00865_amd.build``).  Raises if it
+    is missing: the package has no CPU path."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB_PATH):
+        raise ImportError(f"{_LIB_PATH} is missing; build it with "
+                          "`python -m paper_1704_00865_amd.build`")
+    lib = ctypes.CDLL(_LIB_PATH)
+    vp, i32 = ctypes.c_void_p, ctypes.c_int32
+    lib.wf_ctx_create.argtypes = [ctypes.POINTER(_Shape), ctypes.POINTER(vp)]
+    lib.wf_ctx_create.restype = i32
+    lib.wf_ctx_destroy.argtypes = [vp]
+    lib.wf_ctx_destroy.restype = None
+    lib.wf_schedule_default.argtypes = [ctypes.POINTER(_Schedule)]
+    lib.wf_schedule_default.restype = None
+    lib.wf_solve.argtypes = [vp, ctypes.POINTER(_Inputs), ctypes.POINTER(_Schedule), vp, vp,
+                             ctypes.POINTER(_Report), ctypes.POINTER(ctypes.c_double), vp]
+    lib.wf_solve.restype = i32
+    lib.wf_rfft2.argtypes = [vp, vp, vp, vp]
+    lib.wf_rfft2.restype = i32
+    lib.wf_irfft2.argtypes = [vp, vp, vp, vp]
+    lib.wf_irfft2.restype = i32
+    lib.wf_ctx_set_profiling.argtypes = [vp, i32]
+    lib.wf_ctx_set_profiling.restype = i32
+    lib.wf_supported.argtypes = [i32, i32, i32]
+    lib.wf_supported.restype = i32
+    lib.wf_strerror.argtypes = [i32]
+    lib.wf_strerror.restype = ctypes.c_char_p
+    _lib = lib
+    return lib
+
+
+def strerror(status: int) -> str:
+    if _lib is None:
+        return STATUS.get(status, str(status))
+    return _lib.wf_strerror(int(status)).decode()
+
+
+@dataclass
+class Schedule:
+    """Cooling schedule and solver options (mirrors ``wf_schedule``).
+
+    lambdas: a fixed lambda per sweep (last value repeats); None = adaptive
+    (Section 3.3: start at lambda0, lambda <- lambda^shrink when the residual
+    plateaus, snap to 1)."""
+    lambdas: Optional[Sequence[float]] = None
+    lambda0: float = 1.0e4
+    shrink: float = 0.7
+    plateau: float = 1.0e-2
+    snap: float = 1.0e-3
+    rtol: float = 1.0e-6
+    max_sweeps: int = 20000
+    monitor_every: int = 16
+    beta: Sequence[float] = (0.9, 0.9, 1.0)
+    floor_frac: float = 0.5
+    chain: str = "three"
+    stop_full: bool = False
+
+    def _c(self):
+        s = _Schedule()
+        keep = None
+        if self.lambdas is not None:
+            arr = np.ascontiguousarray(np.asarray(self.lambdas, dtype=np.float64))
+            keep = arr
+            s.kind = 0
+            s.lam = arr.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+            s.n_lambda = arr.size
+        else:
+            s.kind = 1
+            s.n_lambda = 0
+        s.lambda0 = self.lambda0
+        s.shrink_exp = self.shrink
+        s.plateau_rtol = self.plateau
+        s.snap_eps = self.snap
+        s.rtol = self.rtol
+        s.max_sweeps = int(self.max_sweeps)
+        s.monitor_every = int(self.monitor_every)
+        for i in range(3):
+            s.beta[i] = float(self.beta[i])
+        s.floor_frac = self.floor_frac
+        s.chain = CHAINS[self.chain]
+        s.stop_full = 1 if self.stop_full else 0
+        return s, keep
+
+
+def _stream_ptr(torch, device):
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+class Context:
+    """Device workspace for one map shape and precision (``wf_ctx``)."""
+
+    def __init__(self, ny: int, nx: int, precision: str = "f32", device=None):
+        import torch
+        lib = load()
+        self.ny, self.nx = int(ny), int(nx)
+        self.dtype = {"f32": torch.float32, "f64": torch.float64}[precision]
+        self.device = torch.device("cuda", torch.cuda.current_device() if device is None
+                                   else torch.device(device).index or 0)
+        shape = _Shape(self.ny, self.nx, 0 if precision == "f32" else 1)
+        h = ctypes.c_void_p()
+        with torch.cuda.device(self.device):
+            st = lib.wf_ctx_create(ctypes.byref(shape), ctypes.byref(h))
+        if st != 0:
+            raise WFError(st, "wf_ctx_create")
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load().wf_ctx_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_profiling(self, on: bool):
+        load().wf_ctx_set_profiling(self._h, 1 if on else 0)
+
+    def _check(self, t, shape, name, dtype=None):
+        import torch
+        if t is None:
+            return None
+        if not isinstance(t, torch.Tensor) or t.device != self.device:
+            raise ValueError(f"{name} must be a tensor on {self.device}")
+        if tuple(t.shape) != tuple(shape):
+            raise ValueError(f"{name} has shape {tuple(t.shape)}, expected {tuple(shape)}")
+        if t.dtype != (dtype or self.dtype):
+            raise ValueError(f"{name} has dtype {t.dtype}, expected {dtype or self.dtype}")
+        if not t.is_contiguous():
+            raise ValueError(f"{name} must be contiguous")
+        return t
+
+    def solve(self, d, s_k, n_pix, p_oof=None, p_stripe=None, mask=None, *,
+              schedule: Schedule = Schedule(), s_init=None, out=None):
+        """Wiener filter of d.  Returns (s, report dict, trace array)."""
+        import torch
+        lib = load()
+        ny, nx = self.ny, self.nx
+        nh = nx // 2 + 1
+        self._check(d, (ny, nx), "d")
+        self._check(s_k, (ny, nh), "s_k")
+        self._check(n_pix, (ny, nx), "n_pix")
+        self._check(p_oof, (ny, nh), "p_oof")
+        self._check(p_stripe, (ny,), "p_stripe")
+        self._check(mask, (ny, nx), "mask", torch.uint8)
+        self._check(s_init, (ny, nx), "s_init")
+        if out is None:
+            out = torch.empty((ny, nx), dtype=self.dtype, device=self.device)
+        self._check(out, (ny, nx), "out")
+        inp = _Inputs(d.data_ptr(), s_k.data_ptr(), n_pix.data_ptr(),
+                      p_oof.data_ptr() if p_oof is not None else None,
+                      p_stripe.data_ptr() if p_stripe is not None else None,
+                      mask.data_ptr() if mask is not None else None)
+        sch, keep = schedule._c()
+        nrec = -(-schedule.max_sweeps // schedule.monitor_every)
+        trace = np.zeros((nrec, 5), dtype=np.float64)
+        rep = _Report()
+        with torch.cuda.device(self.device):
+            st = lib.wf_solve(self._h, ctypes.byref(inp), ctypes.byref(sch),
+                              s_init.data_ptr() if s_init is not None else None,
+                              out.data_ptr(), ctypes.byref(rep),
+                              trace.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                              _stream_ptr(torch, self.device))
+        del keep
+        if st < 0:
+            raise WFError(st, "wf_solve")
+        report = dict(status=STATUS[st], sweeps=rep.sweeps, n_records=rep.n_records,
+                      n_levels=rep.n_levels, lam=rep.lam, rho=rep.rho, rho_mask=rep.rho_mask,
+                      dd2=rep.dd2, d2=rep.d2, tau=list(rep.tau), phi=rep.phi,
+                      kernel_ms=list(rep.kernel_ms), kernel_launches=list(rep.kernel_launches))
+        return out, report, trace[: rep.n_records]
+
+    def rfft2(self, x):
+        import torch
+        self._check(x, (self.ny, self.nx), "x")
+        cd = torch.complex64 if self.dtype == torch.float32 else torch.complex128
+        X = torch.empty((self.ny, self.nx // 2 + 1), dtype=cd, device=self.device)
+        with torch.cuda.device(self.device):
+            st = load().wf_rfft2(self._h, x.data_ptr(), X.data_ptr(), _stream_ptr(torch, self.device))
+        if st != 0:
+            raise WFError(st, "wf_rfft2")
+        return X
+
+    def irfft2(self, X):
+        import torch
+        cd = torch.complex64 if self.dtype == torch.float32 else torch.complex128
+        self._check(X, (self.ny, self.nx // 2 + 1), "X", cd)
+        x = torch.empty((self.ny, self.nx), dtype=self.dtype, device=self.device)
+        with torch.cuda.device(self.device):
+            st = load().wf_irfft2(self._h, X.data_ptr(), x.data_ptr(), _stream_ptr(torch, self.device))
+        if st != 0:
+            raise WFError(st, "wf_irfft2")
+        return x
+
+
+def solve(d, s_k, n_pix, p_oof=None, p_stripe=None, mask=None, *, schedule=Schedule(),
+          s_init=None):
+    """One-shot solve: creates a context for d's shape and dtype."""
+    import torch
+    prec = "f64" if d.dtype == torch.float64 else "f32"
+    ctx = Context(d.shape[0], d.shape[1], prec, device=d.device)
+    try:
+        return ctx.solve(d, s_k, n_pix, p_oof, p_stripe, mask, schedule=schedule, s_init=s_init)
+    finally:
+        ctx.close()
+
+
+def rfft2(x):
+    import torch
+    ctx = Context(x.shape[0], x.shape[1], "f64" if x.dtype == torch.float64 else "f32",
+                  device=x.device)
+    try:
+        return ctx.rfft2(x)
+    finally:
+        ctx.close()
+
+
+def irfft2(X, nx: int):
+    import torch
+    ctx = Context(X.shape[0], nx, "f64" if X.dtype == torch.complex128 else "f32",
+                  device=X.device)
+    try:
+        return ctx.irfft2(X)
+    finally:
+        ctx.close()

@@ -1,0 +1,212 @@
+// Workgroup FFTs for gfx950: radix-16/8/4 Stockham passes with the data in
+// registers and one LDS exchange between passes.
+//
+// A transform of length N (power of two, 64..4096) is spread over NT = N/16
+// threads that each hold E = 16 complex values.  Register q of thread t holds
+// element t + NT*q both before the first pass and after the last one (natural
+// order), so a transform can be followed by per-element work and by another
+// transform without any reshuffle, and its first loads and last stores are
+// coalesced.  Pass j with radix R and span p (product of the earlier radices)
+// computes, for butterfly i in [0, N/R):
+//     u_m = x[i + m N/R] * w_{pR}^{m (i mod p)},  U = DFT_R(u),
+//     y[(i - i mod p) R + (i mod p) + m p] = U_m,
+// the autosorting Stockham form.  Twiddles w_N^j come from a table built in
+// double precision on the host and rounded once (no device sin/cos).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+namespace wf {
+
+template <class T>
+struct cx {
+  T re, im;
+};
+
+template <class T>
+__device__ __forceinline__ cx<T> operator+(cx<T> a, cx<T> b) { return {a.re + b.re, a.im + b.im}; }
+template <class T>
+__device__ __forceinline__ cx<T> operator-(cx<T> a, cx<T> b) { return {a.re - b.re, a.im - b.im}; }
+template <class T>
+__device__ __forceinline__ cx<T> cmul(cx<T> a, cx<T> b) {
+  return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
+}
+template <class T>
+__device__ __forceinline__ cx<T> cscale(cx<T> a, T s) { return {a.re * s, a.im * s}; }
+
+// multiply by w_4 = -i (forward) or +i (inverse)
+template <class T, bool INV>
+__device__ __forceinline__ cx<T> mul_w4(cx<T> a) {
+  return INV ? cx<T>{-a.im, a.re} : cx<T>{a.im, -a.re};
+}
+
+// cos and sin of j*pi/8, j = 0..15
+__device__ constexpr double kC16[16] = {
+    1.0, 0.92387953251128675613, 0.70710678118654752440, 0.38268343236508977173,
+    0.0, -0.38268343236508977173, -0.70710678118654752440, -0.92387953251128675613,
+    -1.0, -0.92387953251128675613, -0.70710678118654752440, -0.38268343236508977173,
+    0.0, 0.38268343236508977173, 0.70710678118654752440, 0.92387953251128675613};
+__device__ constexpr double kS16[16] = {
+    0.0, 0.38268343236508977173, 0.70710678118654752440, 0.92387953251128675613,
+    1.0, 0.92387953251128675613, 0.70710678118654752440, 0.38268343236508977173,
+    0.0, -0.38268343236508977173, -0.70710678118654752440, -0.92387953251128675613,
+    -1.0, -0.92387953251128675613, -0.70710678118654752440, -0.38268343236508977173};
+
+// w_16^j = exp(-+ 2 pi i j / 16) (minus for the forward transform)
+template <class T, bool INV>
+__device__ __forceinline__ cx<T> w16(int j) {
+  const T c = (T)kC16[j & 15];
+  const T s = (T)kS16[j & 15];
+  return INV ? cx<T>{c, s} : cx<T>{c, -s};
+}
+
+template <class T, bool INV>
+__device__ __forceinline__ void dft2(cx<T>* u) {
+  const cx<T> a = u[0], b = u[1];
+  u[0] = a + b;
+  u[1] = a - b;
+}
+
+template <class T, bool INV>
+__device__ __forceinline__ void dft4(cx<T>& a0, cx<T>& a1, cx<T>& a2, cx<T>& a3) {
+  const cx<T> t0 = a0 + a2, t1 = a0 - a2, t2 = a1 + a3;
+  const cx<T> t3 = mul_w4<T, INV>(a1 - a3);
+  a0 = t0 + t2;
+  a2 = t0 - t2;
+  a1 = t1 + t3;
+  a3 = t1 - t3;
+}
+
+template <class T, bool INV>
+__device__ __forceinline__ void dft4(cx<T>* u) { dft4<T, INV>(u[0], u[1], u[2], u[3]); }
+
+// 8 = 4 (n1) x 2 (n2): n = 2 n1 + n2, k = k1 + 4 k2
+template <class T, bool INV>
+__device__ __forceinline__ void dft8(cx<T>* u) {
+  cx<T> y0[4] = {u[0], u[2], u[4], u[6]};
+  cx<T> y1[4] = {u[1], u[3], u[5], u[7]};
+  dft4<T, INV>(y0);
+  dft4<T, INV>(y1);
+#pragma unroll
+  for (int k1 = 1; k1 < 4; ++k1) y1[k1] = cmul(y1[k1], w16<T, INV>(2 * k1));
+#pragma unroll
+  for (int k1 = 0; k1 < 4; ++k1) {
+    u[k1] = y0[k1] + y1[k1];
+    u[k1 + 4] = y0[k1] - y1[k1];
+  }
+}
+
+// 16 = 4 (n1) x 4 (n2): n = 4 n1 + n2, k = k1 + 4 k2
+template <class T, bool INV>
+__device__ __forceinline__ void dft16(cx<T>* u) {
+  cx<T> y[4][4];
+#pragma unroll
+  for (int n2 = 0; n2 < 4; ++n2) {
+    y[n2][0] = u[n2];
+    y[n2][1] = u[4 + n2];
+    y[n2][2] = u[8 + n2];
+    y[n2][3] = u[12 + n2];
+    dft4<T, INV>(y[n2]);
+  }
+#pragma unroll
+  for (int n2 = 1; n2 < 4; ++n2)
+#pragma unroll
+    for (int k1 = 1; k1 < 4; ++k1) y[n2][k1] = cmul(y[n2][k1], w16<T, INV>(n2 * k1));
+#pragma unroll
+  for (int k1 = 0; k1 < 4; ++k1) {
+    cx<T> a0 = y[0][k1], a1 = y[1][k1], a2 = y[2][k1], a3 = y[3][k1];
+    dft4<T, INV>(a0, a1, a2, a3);
+    u[k1] = a0;
+    u[k1 + 4] = a1;
+    u[k1 + 8] = a2;
+    u[k1 + 12] = a3;
+  }
+}
+
+template <class T, int R, bool INV>
+__device__ __forceinline__ void dft(cx<T>* u) {
+  if constexpr (R == 2) dft2<T, INV>(u);
+  else if constexpr (R == 4) dft4<T, INV>(u);
+  else if constexpr (R == 8) dft8<T, INV>(u);
+  else if constexpr (R == 16) dft16<T, INV>(u);
+}
+
+// LDS index with one pad slot per 16 elements (breaks the stride-16 bank
+// conflicts of the first pass's scattered stores)
+__device__ __forceinline__ int lpad(int j) { return j + (j >> 4); }
+template <int N>
+struct padded {
+  static constexpr int value = N + N / 16;
+};
+
+// radix plan: 16 * R1 * R2 = N
+template <int N>
+struct plan;
+template <> struct plan<64> { static constexpr int r1 = 4, r2 = 1; };
+template <> struct plan<128> { static constexpr int r1 = 8, r2 = 1; };
+template <> struct plan<256> { static constexpr int r1 = 16, r2 = 1; };
+template <> struct plan<512> { static constexpr int r1 = 8, r2 = 4; };
+template <> struct plan<1024> { static constexpr int r1 = 16, r2 = 4; };
+template <> struct plan<2048> { static constexpr int r1 = 16, r2 = 8; };
+template <> struct plan<4096> { static constexpr int r1 = 16, r2 = 16; };
+
+constexpr int kE = 16;  // complex values held by each thread
+
+// One Stockham pass.  reg: the thread's E values; lds: this transform's
+// padded exchange buffer; tw: w_N^j table (forward sign).
+template <class T, int N, int R, int P, bool INV, bool LAST>
+__device__ __forceinline__ void stockham_pass(cx<T>* reg, cx<T>* lds, int t,
+                                              const cx<T>* __restrict__ tw) {
+  constexpr int NT = N / kE;
+  constexpr int NB = kE / R;
+#pragma unroll
+  for (int b = 0; b < NB; ++b) {
+    const int i = t + b * NT;
+    const int k = i & (P - 1);
+    cx<T> u[R];
+#pragma unroll
+    for (int m = 0; m < R; ++m) u[m] = reg[b + m * NB];
+    if constexpr (P > 1) {
+      constexpr int STEP = N / (P * R);
+#pragma unroll
+      for (int m = 1; m < R; ++m) {
+        cx<T> w = tw[m * k * STEP];
+        if (INV) w.im = -w.im;
+        u[m] = cmul(u[m], w);
+      }
+    }
+    dft<T, R, INV>(u);
+    if constexpr (LAST) {
+#pragma unroll
+      for (int m = 0; m < R; ++m) reg[b + m * NB] = u[m];
+    } else {
+      const int j = (i - k) * R + k;
+#pragma unroll
+      for (int m = 0; m < R; ++m) lds[lpad(j + m * P)] = u[m];
+    }
+  }
+  if constexpr (!LAST) {
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < kE; ++q) reg[q] = lds[lpad(t + NT * q)];
+    __syncthreads();
+  }
+}
+
+// Full transform of length N.  Every thread of the workgroup must call it
+// (it contains barriers); lds must hold padded<N>::value elements per
+// transform and must not be in use by the caller.
+template <class T, int N, bool INV>
+__device__ __forceinline__ void fft(cx<T>* reg, cx<T>* lds, int t, const cx<T>* __restrict__ tw) {
+  constexpr int R1 = plan<N>::r1, R2 = plan<N>::r2;
+  if constexpr (R2 == 1) {
+    stockham_pass<T, N, 16, 1, INV, false>(reg, lds, t, tw);
+    stockham_pass<T, N, R1, 16, INV, true>(reg, lds, t, tw);
+  } else {
+    stockham_pass<T, N, 16, 1, INV, false>(reg, lds, t, tw);
+    stockham_pass<T, N, R1, 16, INV, false>(reg, lds, t, tw);
+    stockham_pass<T, N, R2, 16 * R1, INV, true>(reg, lds, t, tw);
+  }
+}
+
+}  // namespace wf

@@ -1,0 +1,674 @@
+// Device code of the multi-messenger Wiener filter (gfx950).
+//
+// One sweep of the iteration (Section 2 equations, data side first) is two
+// launches over a transit buffer B that holds a field transformed along x
+// only (a "row spectrum", half spectrum in k_x):
+//
+//   row kernel    per band of kTR rows: inverse row FFT of d_1's row spectrum
+//                 -> pixel update t_2 = [T_2 d + Nbar_2 d_1] / (Nbar_2 + T_2)
+//                 (eqn 2mess_t1 form, white level) -> forward row FFT of t_2.
+//   column kernel per group of kTC half-spectrum columns: forward column FFT
+//                 -> the Fourier-side chain per mode (eqns 2mess_d0, 2mess_t0,
+//                 2mess_s and their stripe-level analogues) -> inverse
+//                 column FFT of d_1.
+//
+// B is tiled [y/kTR][kx/kTC][kTR][kTC] so that both kernels read and write it
+// in contiguous runs (a row band is one contiguous block; a column group is
+// kTR*kTC*sizeof(complex) contiguous per tile).  Fourier-side state and
+// per-mode coefficients are stored column-major [kx][ky] so the column kernel
+// streams them with consecutive threads on consecutive ky.
+//
+// Fields are stored unnormalised in Fourier space (forward transforms carry
+// no factor); the inverse's 1/(nx ny) is applied once in the row kernel.  All
+// messenger covariances are multiples of the identity, so the update
+// coefficients do not depend on that scale.
+//
+// The residual monitor runs in float64 from the stored state: x = S^-1 s =
+// t_A / (S_chain + T_A) and y = (S + N_Fourier) x go through float64 inverse
+// transforms, and Delta d = y + N_white x - d (Section 2) is summed over
+// observed pixels; x is summed over masked ones.  A one-block controller
+// then applies the cooling schedule on the device.
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+
+#include "wf_fft.hpp"
+#include "wf_kernels.hpp"
+
+namespace wf {
+
+template <int N, int TC>
+struct KP {
+  static constexpr int value = ((N / 2 + 1 + TC - 1) / TC) * TC;
+};
+
+template <class T>
+__device__ __forceinline__ T white_update(T d, T nb, T d1, T lt) {
+  // masked pixel (Nbar = inf, stored as a negative sentinel): t_2 = d_1
+  if (nb < (T)0) return d1;
+  return d1 + (lt / (nb + lt)) * (d - d1);
+}
+
+// ---------------------------------------------------------------------------
+// block reductions (wave64 shuffles, then one LDS round)
+// ---------------------------------------------------------------------------
+enum RedOp { RED_SUM = 0, RED_MIN = 1, RED_MAX = 2 };
+
+template <int OP>
+__device__ __forceinline__ double red2(double a, double b) {
+  if constexpr (OP == RED_SUM) return a + b;
+  if constexpr (OP == RED_MIN) return fmin(a, b);
+  return fmax(a, b);
+}
+
+template <int OP>
+__device__ double block_reduce(double v, double* sh) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v = red2<OP>(v, __shfl_xor(v, off, 64));
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const int nw = (blockDim.x + 63) >> 6;
+  __syncthreads();
+  if (lane == 0) sh[wid] = v;
+  __syncthreads();
+  double r = sh[0];
+  for (int w = 1; w < nw; ++w) r = red2<OP>(r, sh[w]);
+  __syncthreads();
+  return r;
+}
+
+// ---------------------------------------------------------------------------
+// setup: validation statistics
+// ---------------------------------------------------------------------------
+// per block: n_obs, min N_pix(obs), max N_pix(obs), sum d^2 (obs),
+//            #non-finite (d or N_pix on observed), #N_pix <= 0 (observed)
+template <class T>
+__global__ __launch_bounds__(256) void stats_pixels_kernel(const T* __restrict__ d,
+                                                           const T* __restrict__ npix,
+                                                           const uint8_t* __restrict__ mask,
+                                                           int64_t n, double* __restrict__ part) {
+  __shared__ double sh[16];
+  double cnt = 0, mn = INFINITY, mx = -INFINITY, s2 = 0, bad = 0, badn = 0;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    if (mask && mask[i] == 0) continue;
+    const double dv = (double)d[i], nv = (double)npix[i];
+    cnt += 1;
+    if (!isfinite(dv) || !isfinite(nv)) {
+      bad += 1;
+      continue;
+    }
+    if (!(nv > 0)) badn += 1;
+    mn = fmin(mn, nv);
+    mx = fmax(mx, nv);
+    s2 += dv * dv;
+  }
+  cnt = block_reduce<RED_SUM>(cnt, sh);
+  mn = block_reduce<RED_MIN>(mn, sh);
+  mx = block_reduce<RED_MAX>(mx, sh);
+  s2 = block_reduce<RED_SUM>(s2, sh);
+  bad = block_reduce<RED_SUM>(bad, sh);
+  badn = block_reduce<RED_SUM>(badn, sh);
+  if (threadIdx.x == 0) {
+    double* o = part + 8 * blockIdx.x;
+    o[0] = cnt; o[1] = mn; o[2] = mx; o[3] = s2; o[4] = bad; o[5] = badn; o[6] = 0; o[7] = 0;
+  }
+}
+
+// per block: min S, min P_1/f, min over modes of (P_1/f + nx P_st on k_x = 0),
+//            #bad S, #bad P_1/f, #bad P_st (non-finite or negative)
+template <class T>
+__global__ __launch_bounds__(256) void stats_spectra_kernel(const T* __restrict__ sk,
+                                                            const T* __restrict__ poof,
+                                                            const T* __restrict__ pst,
+                                                            int ny, int nx, double* __restrict__ part) {
+  __shared__ double sh[16];
+  const int nh = nx / 2 + 1;
+  const int64_t n = (int64_t)ny * nh;
+  double ms = INFINITY, mo = INFINITY, mf = INFINITY, bs = 0, bo = 0, bp = 0;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const int ky = (int)(i / nh), kx = (int)(i - (int64_t)ky * nh);
+    const double s = (double)sk[i];
+    if (!isfinite(s) || s < 0) bs += 1;
+    ms = fmin(ms, s);
+    double f = 0;
+    if (poof) {
+      const double o = (double)poof[i];
+      if (!isfinite(o) || o < 0) bo += 1;
+      mo = fmin(mo, o);
+      f = o;
+    }
+    if (pst && kx == 0) {
+      const double p = (double)pst[ky];
+      if (!isfinite(p) || p < 0) bp += 1;
+      f += (double)nx * p;
+    }
+    mf = fmin(mf, f);
+  }
+  ms = block_reduce<RED_MIN>(ms, sh);
+  mo = block_reduce<RED_MIN>(mo, sh);
+  mf = block_reduce<RED_MIN>(mf, sh);
+  bs = block_reduce<RED_SUM>(bs, sh);
+  bo = block_reduce<RED_SUM>(bo, sh);
+  bp = block_reduce<RED_SUM>(bp, sh);
+  if (threadIdx.x == 0) {
+    double* o = part + 8 * blockIdx.x;
+    o[0] = ms; o[1] = mo; o[2] = mf; o[3] = bs; o[4] = bo; o[5] = bp; o[6] = 0; o[7] = 0;
+  }
+}
+
+// reduce per-block statistics in a fixed order; ops[j] says how column j
+// combines (sum / min / max)
+__global__ __launch_bounds__(64) void stats_finalize_kernel(const double* __restrict__ part, int nblk,
+                                                            int4 ops_lo, int4 ops_hi,
+                                                            double* __restrict__ out) {
+  const int j = threadIdx.x;
+  if (j >= 8) return;
+  const int ops[8] = {ops_lo.x, ops_lo.y, ops_lo.z, ops_lo.w, ops_hi.x, ops_hi.y, ops_hi.z, ops_hi.w};
+  const int op = ops[j];
+  double r = part[j];
+  for (int b = 1; b < nblk; ++b) {
+    const double v = part[8 * b + j];
+    r = op == RED_SUM ? r + v : (op == RED_MIN ? fmin(r, v) : fmax(r, v));
+  }
+  out[j] = r;
+}
+
+// ---------------------------------------------------------------------------
+// setup: per-pixel and per-mode coefficients
+// ---------------------------------------------------------------------------
+template <class T>
+__global__ __launch_bounds__(256) void prep_pixels_kernel(const T* __restrict__ npix,
+                                                          const uint8_t* __restrict__ mask, int64_t n,
+                                                          double sub, T* __restrict__ nbar2) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const bool obs = !mask || mask[i] != 0;
+    nbar2[i] = obs ? (T)((double)npix[i] - sub) : (T)(-1);
+  }
+}
+
+// column-major [kx][ky] per-mode arrays:
+//   sc  = covariance at the signal end of the chain (S, or S + N_F for the
+//         augmented chain, plus the lent floor when it sits in N_F)
+//   nbA = Nbar of the array level = N_A - tau_A
+//   sy  = S + N_1/f + N_stripe (true Fourier noise; the white level is added
+//         in pixel space by the monitor)
+//   sig = S
+
+
+template <class T>
+__global__ __launch_bounds__(256) void prep_spectra_kernel(const T* __restrict__ sk,
+                                                           const T* __restrict__ poof,
+                                                           const T* __restrict__ pst, PrepSpecArgs a,
+                                                           T* __restrict__ sc, T* __restrict__ nbA,
+                                                           T* __restrict__ sy, T* __restrict__ sig) {
+  const int nh = a.nx / 2 + 1;
+  const int64_t n = (int64_t)a.ny * nh;
+  for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < n;
+       j += (int64_t)gridDim.x * blockDim.x) {
+    const int kx = (int)(j / a.ny), ky = (int)(j - (int64_t)kx * a.ny);
+    const int64_t i = (int64_t)ky * nh + kx;  // row-major source index
+    const double s = (double)sk[i];
+    const double o = a.has_oof ? (double)poof[i] : 0.0;
+    const double st = (a.has_st && kx == 0) ? (double)a.nx * (double)pst[ky] : 0.0;
+    const double nf = o + st;
+    sc[j] = (T)(a.sc_adds_nf ? s + nf + a.phi_nf : s);
+    if (a.nbA_kind == 1) nbA[j] = (T)(o - a.tauA);
+    else if (a.nbA_kind == 2) nbA[j] = (T)(nf + a.phi_nf - a.tauA);
+    sy[j] = (T)(s + nf);
+    sig[j] = (T)s;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// row kernel: inverse row FFT -> white-level update -> forward row FFT
+// ---------------------------------------------------------------------------
+template <class T, int NX, int MODE>
+__global__ __launch_bounds__((kTR / 2) * (NX / kE)) void row_kernel(SweepArgs<T> a, int k_local,
+                                                                    const T* __restrict__ xin,
+                                                                    T* __restrict__ xout) {
+  constexpr int NT = NX / kE;
+  constexpr int RP = kTR / 2;
+  constexpr int KPc = KP<NX, kTC>::value;
+  constexpr int BAND = kTR * KPc;
+  constexpr int XS = padded<NX>::value;
+  constexpr int LDSN = (BAND > RP * XS) ? BAND : RP * XS;
+  __shared__ cx<T> lds[LDSN];
+
+  T lt = (T)0;  // lambda * tau of the white level
+  if constexpr (MODE == ROW_SWEEP) {
+    const DevSched* s = a.sch;
+    if (s->done) return;
+    const int kk = s->base + k_local;
+    if (kk >= s->max_sweeps) return;
+    lt = (T)(a.lam[kk] * a.tauW);
+  }
+  const int tid = threadIdx.x;
+  const int band = blockIdx.x;
+  cx<T>* gB = (cx<T>*)a.B + (size_t)band * BAND;
+  const cx<T>* tw = (const cx<T>*)a.twx;
+  const int p = tid / NT, t = tid - p * NT;
+  const int y0 = band * kTR + 2 * p;
+  cx<T> reg[kE];
+
+  if constexpr (MODE == ROW_SWEEP || MODE == ROW_C2R) {
+    for (int e = tid; e < BAND; e += blockDim.x) lds[e] = gB[e];
+    __syncthreads();
+    // Z = A + i B for the row pair (2p, 2p+1); A, B Hermitian in k_x
+#pragma unroll
+    for (int q = 0; q < kE; ++q) {
+      const int k = t + NT * q;
+      const bool hi = k > NX / 2;
+      const int kx = hi ? NX - k : k;
+      const int li = (kx / kTC) * (kTR * kTC) + (2 * p) * kTC + (kx % kTC);
+      cx<T> A = lds[li], Bv = lds[li + kTC];
+      if (kx == 0 || kx == NX / 2) {
+        A.im = (T)0;
+        Bv.im = (T)0;
+      }
+      if (hi) {
+        A.im = -A.im;
+        Bv.im = -Bv.im;
+      }
+      reg[q] = cx<T>{A.re - Bv.im, A.im + Bv.re};
+    }
+    __syncthreads();
+    fft<T, NX, true>(reg, lds + p * XS, t, tw);
+    const T sc = (T)a.scale;
+    if constexpr (MODE == ROW_C2R) {
+#pragma unroll
+      for (int q = 0; q < kE; ++q) {
+        const size_t i0 = (size_t)y0 * NX + t + NT * q;
+        xout[i0] = reg[q].re * sc;
+        xout[i0 + NX] = reg[q].im * sc;
+      }
+      return;
+    } else {
+#pragma unroll
+      for (int q = 0; q < kE; ++q) {
+        const size_t i0 = (size_t)y0 * NX + t + NT * q;
+        const size_t i1 = i0 + NX;
+        const T d1a = reg[q].re * sc, d1b = reg[q].im * sc;
+        reg[q] = cx<T>{white_update<T>(a.d[i0], a.nbar2[i0], d1a, lt),
+                       white_update<T>(a.d[i1], a.nbar2[i1], d1b, lt)};
+      }
+    }
+  } else {  // ROW_R2C
+#pragma unroll
+    for (int q = 0; q < kE; ++q) {
+      const size_t i0 = (size_t)y0 * NX + t + NT * q;
+      reg[q] = cx<T>{xin[i0], xin[i0 + NX]};
+    }
+  }
+  fft<T, NX, false>(reg, lds + p * XS, t, tw);
+#pragma unroll
+  for (int q = 0; q < kE; ++q) lds[p * XS + lpad(t + NT * q)] = reg[q];
+  __syncthreads();
+  // split Z into the two rows' spectra and store the band in tile order
+  for (int e = tid; e < BAND; e += blockDim.x) {
+    const int tile = e / (kTR * kTC);
+    const int w = e - tile * (kTR * kTC);
+    const int r = w / kTC, c = w - r * kTC;
+    const int kx = tile * kTC + c;
+    cx<T> v = {(T)0, (T)0};
+    if (kx <= NX / 2) {
+      const cx<T>* Z = lds + (r >> 1) * XS;
+      const cx<T> zk = Z[lpad(kx)], zm = Z[lpad((NX - kx) & (NX - 1))];
+      v = (r & 1) ? cx<T>{(zk.im + zm.im) * (T)0.5, (zm.re - zk.re) * (T)0.5}
+                  : cx<T>{(zk.re + zm.re) * (T)0.5, (zk.im - zm.im) * (T)0.5};
+    }
+    gB[e] = v;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// column kernel: forward column FFT -> Fourier-side chain -> inverse FFT
+// ---------------------------------------------------------------------------
+template <class T>
+__device__ __forceinline__ cx<T> wavg(T wa, cx<T> a, T wb, cx<T> b, T inv) {
+  return cx<T>{(wa * a.re + wb * b.re) * inv, (wa * a.im + wb * b.im) * inv};
+}
+
+template <class T, int NY, int MODE>
+__global__ __launch_bounds__(kTC * (NY / kE)) void col_kernel(SweepArgs<T> a, int k_local,
+                                                              cx<T>* __restrict__ spec,
+                                                              double lam_init) {
+  constexpr int NT = NY / kE;
+  constexpr int YS = padded<NY>::value;
+  constexpr int TRTC = kTR * kTC;
+  __shared__ cx<T> lds[kTC * YS];
+
+  double lam = 0.0, lamp = 0.0;
+  bool store_first = false;
+  if constexpr (MODE == COL_SWEEP) {
+    const DevSched* s = a.sch;
+    if (s->done) return;
+    const int base = s->base;
+    const int kk = base + k_local;
+    if (kk >= s->max_sweeps) return;
+    lam = a.lam[kk];
+    lamp = a.lam[kk > 0 ? kk - 1 : 0];
+    const int klast = min(base + s->K, s->max_sweeps) - 1;
+    store_first = (kk == klast);
+  }
+  const int tid = threadIdx.x;
+  const int g = blockIdx.x;
+  const int G = a.kp / kTC;
+  const int c = tid / NT, t = tid - c * NT;
+  const int kx = g * kTC + c;
+  const int nh = a.nx / 2 + 1;
+  const bool valid = kx < nh;
+  cx<T>* gB = (cx<T>*)a.B;
+  const cx<T>* tw = (const cx<T>*)a.twy;
+  cx<T> reg[kE];
+
+  if constexpr (MODE == COL_INV_IN) {
+#pragma unroll
+    for (int q = 0; q < kE; ++q) {
+      const int ky = t + NT * q;
+      reg[q] = valid ? spec[(size_t)ky * nh + kx] : cx<T>{(T)0, (T)0};
+    }
+  } else {
+    for (int e = tid; e < kTC * NY; e += blockDim.x) {
+      const int yb = e / TRTC, w = e - yb * TRTC;
+      const int r = w / kTC, cc = w - r * kTC;
+      lds[cc * YS + lpad(yb * kTR + r)] = gB[((size_t)yb * G + g) * TRTC + w];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < kE; ++q) reg[q] = lds[c * YS + lpad(t + NT * q)];
+    __syncthreads();
+    fft<T, NY, false>(reg, lds + c * YS, t, tw);
+  }
+
+  if constexpr (MODE == COL_FWD_OUT) {
+    if (valid) {
+#pragma unroll
+      for (int q = 0; q < kE; ++q) spec[(size_t)(t + NT * q) * nh + kx] = reg[q];
+    }
+    return;
+  }
+
+  if constexpr (MODE == COL_SWEEP) {
+    const T TW = (T)(lam * a.tauW), TA = (T)(lam * a.tauA), TB = (T)(lam * a.tauB);
+    const T SA = (T)(lamp * a.tauA);
+    cx<T>* tA = (cx<T>*)a.tA;
+    cx<T>* dA = (cx<T>*)a.dA;
+    cx<T>* tB = (cx<T>*)a.tB;
+    const T cB = (T)a.cB;
+    const T nxr = (T)a.nx;
+    if (valid) {
+#pragma unroll
+      for (int q = 0; q < kE; ++q) {
+        const int ky = t + NT * q;
+        const size_t idx = (size_t)kx * NY + ky;
+        const cx<T> t2 = reg[q];
+        const T s = a.sc[idx];
+        cx<T> out;
+        if (a.fk == FK_NONE) {
+          out = cscale(t2, s / (s + TW));
+          if (store_first) tA[idx] = t2;
+        } else if (a.fk == FK_ARRAY_STRIPE) {
+          const T nbB = (kx == 0 ? nxr * a.pst[ky] : (T)0) + cB;
+          const T nbA = a.nbA[idx];
+          const cx<T> tBo = tB[idx], dAo = dA[idx], tAo = tA[idx];
+          const cx<T> dBn = wavg(nbB, t2, TW, tBo, (T)1 / (nbB + TW));
+          const cx<T> tBn = wavg(TB, dBn, nbB, dAo, (T)1 / (nbB + TB));
+          const cx<T> dAn = wavg(nbA, tBn, TB, tAo, (T)1 / (nbA + TB));
+          const cx<T> so = cscale(tAo, s / (s + SA));
+          const cx<T> tAn = wavg(TA, dAn, nbA, so, (T)1 / (nbA + TA));
+          tB[idx] = tBn;
+          dA[idx] = dAn;
+          tA[idx] = tAn;
+          out = dBn;
+        } else {  // one Fourier level: an array level or the stripe level
+          const T nbA = (a.fk == FK_ARRAY) ? a.nbA[idx] : (kx == 0 ? nxr * a.pst[ky] : (T)0) + cB;
+          const cx<T> tAo = tA[idx];
+          const cx<T> dAn = wavg(nbA, t2, TW, tAo, (T)1 / (nbA + TW));
+          const cx<T> so = cscale(tAo, s / (s + SA));
+          const cx<T> tAn = wavg(TA, dAn, nbA, so, (T)1 / (nbA + TA));
+          tA[idx] = tAn;
+          out = dAn;
+        }
+        reg[q] = out;
+      }
+    } else {
+#pragma unroll
+      for (int q = 0; q < kE; ++q) reg[q] = cx<T>{(T)0, (T)0};
+    }
+  }
+
+  if constexpr (MODE == COL_INIT) {
+    // warm start: every stored field = s_init; the field handed to the white
+    // level is s_init too, except for a chain without Fourier level, where it
+    // is the signal-end field S_c (S_c + lambda_0 tau)^-1 s_init
+    cx<T>* tA = (cx<T>*)a.tA;
+    cx<T>* dA = (cx<T>*)a.dA;
+    cx<T>* tB = (cx<T>*)a.tB;
+    const T TW0 = (T)(lam_init * a.tauW);
+#pragma unroll
+    for (int q = 0; q < kE; ++q) {
+      const int ky = t + NT * q;
+      const size_t idx = (size_t)kx * NY + ky;
+      cx<T> v = reg[q];
+      if (valid) {
+        if (a.fk == FK_NONE) {
+          const T s = a.sc[idx];
+          v = cscale(v, s / (s + TW0));
+        } else {
+          tA[idx] = v;
+          if (a.fk == FK_ARRAY_STRIPE) {
+            dA[idx] = v;
+            tB[idx] = v;
+          }
+        }
+      } else {
+        v = cx<T>{(T)0, (T)0};
+      }
+      reg[q] = v;
+    }
+  }
+
+  fft<T, NY, true>(reg, lds + c * YS, t, tw);
+#pragma unroll
+  for (int q = 0; q < kE; ++q) lds[c * YS + lpad(t + NT * q)] = reg[q];
+  __syncthreads();
+  for (int e = tid; e < kTC * NY; e += blockDim.x) {
+    const int yb = e / TRTC, w = e - yb * TRTC;
+    const int r = w / kTC, cc = w - r * kTC;
+    gB[((size_t)yb * G + g) * TRTC + w] = lds[cc * YS + lpad(yb * kTR + r)];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// float64 residual monitor and output
+// ---------------------------------------------------------------------------
+
+
+__device__ __forceinline__ bool monitor_active(const DevSched* s, double* lam_last,
+                                               const double* lam) {
+  if (s->done) return false;
+  const int klast = min(s->base + s->K, s->max_sweeps) - 1;
+  *lam_last = lam[klast];
+  return true;
+}
+
+template <class T, int NY>
+__global__ __launch_bounds__(kTCM * (NY / kE)) void mon_col_kernel(MonArgs<T> m, int mode,
+                                                                   double lam_out) {
+  constexpr int NT = NY / kE;
+  constexpr int YS = padded<NY>::value;
+  constexpr int TRTC = kTRM * kTCM;
+  __shared__ cx<double> lds[kTCM * YS];
+  double lamv = lam_out;
+  if (mode == MON_RESIDUAL && !monitor_active(m.sch, &lamv, m.lam)) return;
+  const int tid = threadIdx.x, g = blockIdx.x, G = m.kpm / kTCM;
+  const int c = tid / NT, t = tid - c * NT;
+  const int kx = g * kTCM + c;
+  const bool valid = kx < m.nx / 2 + 1;
+  const double Tf = lamv * m.tau_first;
+  const cx<T>* tf = (const cx<T>*)m.tfirst;
+  cx<double> rx[kE], ry[kE];
+#pragma unroll
+  for (int q = 0; q < kE; ++q) {
+    const int ky = t + NT * q;
+    const size_t idx = (size_t)kx * NY + ky;
+    if (valid) {
+      const cx<T> v = tf[idx];
+      const double inv = 1.0 / ((double)m.sc[idx] + Tf);
+      const cx<double> x = {(double)v.re * inv, (double)v.im * inv};
+      const double f = (mode == MON_OUTPUT) ? (double)m.sig[idx] : (double)m.sy[idx];
+      rx[q] = x;
+      ry[q] = cx<double>{x.re * f, x.im * f};
+    } else {
+      rx[q] = cx<double>{0.0, 0.0};
+      ry[q] = cx<double>{0.0, 0.0};
+    }
+  }
+#pragma unroll
+  for (int field = 0; field < 2; ++field) {
+    cx<double>* reg = field == 0 ? rx : ry;
+    cx<double>* dst = field == 0 ? m.Mx : m.My;
+    fft<double, NY, true>(reg, lds + c * YS, t, m.twy);
+#pragma unroll
+    for (int q = 0; q < kE; ++q) lds[c * YS + lpad(t + NT * q)] = reg[q];
+    __syncthreads();
+    for (int e = tid; e < kTCM * NY; e += blockDim.x) {
+      const int yb = e / TRTC, w = e - yb * TRTC;
+      const int r = w / kTCM, cc = w - r * kTCM;
+      dst[((size_t)yb * G + g) * TRTC + w] = lds[cc * YS + lpad(yb * kTRM + r)];
+    }
+    __syncthreads();
+  }
+}
+
+template <class T, int NX>
+__global__ __launch_bounds__(kTRM * (NX / kE)) void mon_row_kernel(MonArgs<T> m, int mode,
+                                                                   T* __restrict__ s_out) {
+  constexpr int NT = NX / kE;
+  constexpr int KPm = KP<NX, kTCM>::value;
+  constexpr int BANDm = kTRM * KPm;
+  constexpr int XS = padded<NX>::value;
+  constexpr int LDSN = (2 * BANDm > kTRM * XS) ? 2 * BANDm : kTRM * XS;
+  __shared__ cx<double> lds[LDSN];
+  __shared__ double sh[32];
+  double lamv = 0.0;
+  if (mode == MON_RESIDUAL && !monitor_active(m.sch, &lamv, m.lam)) return;
+  const int tid = threadIdx.x, band = blockIdx.x;
+  const cx<double>* gx = m.Mx + (size_t)band * BANDm;
+  const cx<double>* gy = m.My + (size_t)band * BANDm;
+  for (int e = tid; e < BANDm; e += blockDim.x) {
+    lds[e] = gx[e];
+    lds[BANDm + e] = gy[e];
+  }
+  __syncthreads();
+  const int r = tid / NT, t = tid - r * NT;
+  cx<double> reg[kE];
+#pragma unroll
+  for (int q = 0; q < kE; ++q) {
+    const int k = t + NT * q;
+    const bool hi = k > NX / 2;
+    const int kx = hi ? NX - k : k;
+    const int li = (kx / kTCM) * (kTRM * kTCM) + r * kTCM + (kx % kTCM);
+    cx<double> X = lds[li], Y = lds[BANDm + li];
+    if (kx == 0 || kx == NX / 2) {
+      X.im = 0.0;
+      Y.im = 0.0;
+    }
+    if (hi) {
+      X.im = -X.im;
+      Y.im = -Y.im;
+    }
+    reg[q] = cx<double>{X.re - Y.im, X.im + Y.re};
+  }
+  __syncthreads();
+  fft<double, NX, true>(reg, lds + r * XS, t, m.twx);
+  const int y = band * kTRM + r;
+  double a_dd = 0.0, a_mx = 0.0;
+#pragma unroll
+  for (int q = 0; q < kE; ++q) {
+    const size_t i = (size_t)y * NX + t + NT * q;
+    const double xv = reg[q].re * m.scale, yv = reg[q].im * m.scale;
+    if (mode == MON_OUTPUT) {
+      s_out[i] = (T)yv;
+    } else if (m.nbar2[i] >= (T)0) {
+      const double dd = yv + (double)m.npix[i] * xv - (double)m.d[i];
+      a_dd += dd * dd;
+    } else {
+      a_mx += xv * xv;
+    }
+  }
+  if (mode == MON_OUTPUT) return;
+  a_dd = block_reduce<RED_SUM>(a_dd, sh);
+  a_mx = block_reduce<RED_SUM>(a_mx, sh);
+  if (tid == 0) {
+    m.part[2 * band] = a_dd;
+    m.part[2 * band + 1] = a_mx;
+  }
+}
+
+// One block: fixed-order reduction of the monitor partials, then the cooling
+// schedule (fixed array, or the plateau rule of Section 3.3) and the stop test.
+__global__ __launch_bounds__(256) void controller_kernel(DevSched* s, double* lam,
+                                                         const double* __restrict__ part, int nblk,
+                                                         double* __restrict__ trace) {
+  __shared__ double sh[16];
+  if (s->done) return;
+  double a = 0.0, b = 0.0;
+  for (int i = threadIdx.x; i < nblk; i += blockDim.x) {
+    a += part[2 * i];
+    b += part[2 * i + 1];
+  }
+  a = block_reduce<RED_SUM>(a, sh);
+  b = block_reduce<RED_SUM>(b, sh);
+  if (threadIdx.x != 0) return;
+  const int klast = min(s->base + s->K, s->max_sweeps) - 1;
+  const double l = lam[klast];
+  const double rho = sqrt(a / s->d2);
+  const double rho_mask = s->nu * sqrt(b) / sqrt(s->d2);
+  if (s->n_rec < s->max_rec) {
+    double* r = trace + 5 * s->n_rec;
+    r[0] = (double)klast;
+    r[1] = l;
+    r[2] = rho;
+    r[3] = a;
+    r[4] = rho_mask;
+    s->n_rec = s->n_rec + 1;
+  }
+  s->rho = rho;
+  s->rho_mask = rho_mask;
+  s->dd2 = a;
+  s->lam_last = l;
+  s->sweeps_done = klast + 1;
+  const double test = s->stop_full ? hypot(rho, rho_mask) : rho;
+  if (!isfinite(a) || !isfinite(b)) {
+    s->status = -3;  // WF_ENONFINITE
+    s->done = 1;
+  } else if (l == 1.0 && test <= s->rtol) {
+    s->status = 0;
+    s->done = 1;
+  } else if (klast + 1 >= s->max_sweeps) {
+    s->status = 1;  // WF_NOT_CONVERGED
+    s->done = 1;
+  } else if (s->adaptive) {
+    double ln = l;
+    if (s->have_prev && fabs(a - s->dd2_prev) < s->plateau * (double)(klast - s->k_prev) * a) {
+      ln = pow(l, s->shrink);
+      if (ln - 1.0 < s->snap) ln = 1.0;
+    }
+    const int end = min(klast + s->K, s->max_sweeps - 1);
+    for (int k = klast + 1; k <= end; ++k) lam[k] = ln;
+    s->dd2_prev = a;
+    s->k_prev = klast;
+    s->have_prev = 1;
+  }
+  s->base = klast + 1;
+}
+
+// ---------------------------------------------------------------------------
+// explicit instantiations and launch helpers (host-callable, C++ linkage)
+// ---------------------------------------------------------------------------
+}  // namespace wf
+
+#include "wf_launch.inc"

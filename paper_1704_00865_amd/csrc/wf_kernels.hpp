@@ -1,0 +1,105 @@
+// Kernel-side data structures shared by wf_kernels.hip and the host runtime.
+#pragma once
+
+#include <stdint.h>
+
+#include "wf_fft.hpp"
+
+namespace wf {
+
+// transit-buffer tile of the sweep (rows x half-spectrum columns per tile)
+constexpr int kTR = 8;
+constexpr int kTC = 4;
+// tile of the float64 monitor transit buffers
+constexpr int kTRM = 2;
+constexpr int kTCM = 2;
+
+// Fourier side of the messenger chain (levels between the signal and the
+// pixel-space white level)
+enum FourierKind : int32_t {
+  FK_NONE = 0,          // no Fourier level: augmented chain or white noise only
+  FK_ARRAY = 1,         // one level, Nbar from an array (1/f alone, or merged)
+  FK_STRIPE = 2,        // one level, the stripe level (no 1/f term)
+  FK_ARRAY_STRIPE = 3,  // 1/f level (signal side) then the stripe level
+};
+
+enum RowMode : int32_t { ROW_SWEEP = 0, ROW_R2C = 1, ROW_C2R = 2 };
+enum ColMode : int32_t { COL_SWEEP = 0, COL_FWD_OUT = 1, COL_INV_IN = 2, COL_INIT = 3 };
+enum MonMode : int32_t { MON_RESIDUAL = 0, MON_OUTPUT = 1 };
+
+// Schedule state resident on the device.  Sweep kernels read it; only the
+// controller kernel (after each monitor) writes it.
+struct DevSched {
+  int32_t base;        // first sweep of the current chunk
+  int32_t done;        // 1: converged / failed / budget spent -> kernels skip
+  int32_t status;      // wf_status once done
+  int32_t max_sweeps;
+  int32_t K;           // sweeps per chunk (monitor interval)
+  int32_t adaptive;
+  int32_t n_rec;       // trace records written
+  int32_t max_rec;
+  int32_t have_prev;
+  int32_t k_prev;
+  int32_t stop_full;
+  int32_t sweeps_done;
+  double shrink, plateau, snap, rtol;
+  double d2;           // sum of d^2 over observed pixels
+  double nu;           // largest observed white variance
+  double dd2_prev;
+  double rho, rho_mask, dd2, lam_last;
+};
+
+template <class T>
+struct SweepArgs {
+  void* B;                // transit buffer, cx<T>, tiled [y/TR][kx/TC][TR][TC]
+  void* tA;               // state: t of the signal-side Fourier level (or t_white copy)
+  void* dA;               // state: d of that level (FK_ARRAY_STRIPE only)
+  void* tB;               // state: t of the stripe level (FK_ARRAY_STRIPE only)
+  const T* sc;            // [kx][ky] covariance of the chain's signal end
+  const T* nbA;           // [kx][ky] Nbar of the array level
+  const T* pst;           // [ny] stripe mode variance (caller's array)
+  const T* d;             // [ny][nx] data (caller's array)
+  const T* nbar2;         // [ny][nx] Nbar of the white level, < 0 where masked
+  const void* twx;        // w_nx^j table, cx<T>
+  const void* twy;        // w_ny^j table, cx<T>
+  const DevSched* sch;
+  const double* lam;      // lambda per sweep index
+  int32_t nx, ny, kp;     // kp: padded half width (multiple of kTC)
+  int32_t fk;             // FourierKind
+  double tauA, tauB, tauW;  // messenger variances (A: signal-side level)
+  double cB;              // Nbar offset of a stripe level (phi - tau)
+  double scale;           // 1 / (nx ny)
+};
+
+// per-mode coefficient preparation (see prep_spectra_kernel)
+struct PrepSpecArgs {
+  int ny, nx;
+  int has_oof, has_st;
+  int sc_adds_nf;      // augmented chain: sc = S + N_F (+ phi_nf)
+  int nbA_kind;        // 0 none, 1: P_1/f - tau, 2: N_F (+phi_nf) - tau
+  double phi_nf;       // floor added to N_F when the stripes have no 1/f partner
+  double tauA;
+};
+
+template <class T>
+struct MonArgs {
+  const void* tfirst;   // cx<T> [kx][ky]: t of the chain's signal-end level
+  const T* sc;          // [kx][ky] S_chain
+  const T* sy;          // [kx][ky] S + N_Fourier
+  const T* sig;         // [kx][ky] S
+  const T* d;           // [ny][nx]
+  const T* npix;        // [ny][nx] caller's white variance
+  const T* nbar2;       // [ny][nx] sign marks the mask
+  cx<double>* Mx;       // monitor transit, tiled [y/kTRM][kx/kTCM][kTRM][kTCM]
+  cx<double>* My;
+  const cx<double>* twx;  // float64 twiddles
+  const cx<double>* twy;
+  const DevSched* sch;
+  const double* lam;
+  double* part;         // per-block (sum dd^2, sum masked x^2)
+  int nx, ny, kpm;      // kpm: padded half width (multiple of kTCM)
+  double tau_first;
+  double scale;
+};
+
+}  // namespace wf

@@ -1,0 +1,31 @@
+// Host-callable launch helpers for the kernels in wf_kernels.hip.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "wf_kernels.hpp"
+
+namespace wf {
+
+template <class T>
+hipError_t launch_row(int mode, const SweepArgs<T>& a, int k_local, const T* xin, T* xout,
+                      hipStream_t st);
+template <class T>
+hipError_t launch_col(int mode, const SweepArgs<T>& a, int k_local, void* spec, double lam_init,
+                      hipStream_t st);
+template <class T>
+hipError_t launch_mon_col(const MonArgs<T>& m, int mode, double lam_out, hipStream_t st);
+template <class T>
+hipError_t launch_mon_row(const MonArgs<T>& m, int mode, T* s_out, hipStream_t st);
+hipError_t launch_controller(DevSched* s, double* lam, const double* part, int nblk, double* trace,
+                             hipStream_t st);
+template <class T>
+hipError_t launch_stats(const T* d, const T* npix, const uint8_t* mask, const T* sk, const T* poof,
+                        const T* pst, int ny, int nx, double* part, int nblk, double* out_pix,
+                        double* out_spec, hipStream_t st);
+template <class T>
+hipError_t launch_prep(const T* npix, const uint8_t* mask, int ny, int nx, double sub, T* nbar2,
+                       const T* sk, const T* poof, const T* pst, const PrepSpecArgs& pa, T* sc, T* nbA,
+                       T* sy, T* sig, hipStream_t st);
+
+}  // namespace wf

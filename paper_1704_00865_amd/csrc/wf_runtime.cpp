@@ -1,0 +1,606 @@
+// Host runtime of the Wiener-filter library: context, validation, messenger
+// set-up, the sweep loop with a device-resident cooling schedule, and the
+// C ABI declared in include/wf.h.
+//
+// The loop enqueues chunks of K sweeps (2 launches each), then the float64
+// monitor (2 launches) and the one-block controller that evaluates the
+// schedule on the device.  The host never waits inside a chunk: it copies the
+// controller's state to pinned memory after each chunk and checks it two
+// chunks later, so the GPU keeps a queue of work; sweeps enqueued after
+// convergence see the device's done flag and return at once, which keeps the
+// result identical whatever the run-ahead.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "wf.h"
+#include "wf_launch.hpp"
+
+using namespace wf;
+
+namespace {
+
+constexpr int kStatBlocks = 256;
+constexpr int kRing = 4;   // pinned readback slots
+constexpr int kLag = 2;    // chunks between enqueue and the host's check
+constexpr int kProfSlots = 512;
+
+struct Ctx {
+  int ny = 0, nx = 0, prec = 0;
+  int nh = 0, kp = 0, kpm = 0;
+  size_t esz = 0;
+  int device = 0;
+  void* B = nullptr;
+  void* tA = nullptr;
+  void* dA = nullptr;
+  void* tB = nullptr;
+  void* sc = nullptr;
+  void* nbA = nullptr;
+  void* sy = nullptr;
+  void* sig = nullptr;
+  void* nbar2 = nullptr;
+  void* twx = nullptr;
+  void* twy = nullptr;
+  cx<double>* twx_d = nullptr;
+  cx<double>* twy_d = nullptr;
+  cx<double>* Mx = nullptr;
+  cx<double>* My = nullptr;
+  double* part = nullptr;
+  double* stats = nullptr;
+  DevSched* sch = nullptr;
+  double* lam = nullptr;
+  int lam_cap = 0;
+  double* trace = nullptr;
+  int trace_cap = 0;
+  DevSched* h_ring = nullptr;  // pinned
+  double* h_stats = nullptr;   // pinned
+  hipEvent_t ev_ring[kRing] = {};
+  int profiling = 0;
+  std::vector<hipEvent_t> prof_ev;
+};
+
+wf_status from_hip(hipError_t e) {
+  if (e == hipSuccess) return WF_OK;
+  if (e == hipErrorOutOfMemory) return WF_ENOMEM;
+  return WF_EDEVICE;
+}
+
+#define WF_TRY(expr)                      \
+  do {                                    \
+    hipError_t e_ = (expr);               \
+    if (e_ != hipSuccess) return from_hip(e_); \
+  } while (0)
+
+bool pow2_in(int n, int lo, int hi) { return n >= lo && n <= hi && (n & (n - 1)) == 0; }
+
+int supported(int ny, int nx, int prec) {
+  const int hi = prec == WF_F64 ? 2048 : 4096;
+  if (prec != WF_F32 && prec != WF_F64) return 0;
+  return pow2_in(ny, 64, hi) && pow2_in(nx, 64, hi);
+}
+
+template <class T>
+void make_table(std::vector<T>& out, int n) {
+  out.resize(2 * (size_t)n);
+  for (int j = 0; j < n; ++j) {
+    const double ang = 2.0 * M_PI * (double)j / (double)n;
+    out[2 * j] = (T)std::cos(ang);
+    out[2 * j + 1] = (T)(-std::sin(ang));
+  }
+}
+
+void free_ctx(Ctx* c) {
+  void* bufs[] = {c->B, c->tA, c->dA, c->tB, c->sc, c->nbA, c->sy, c->sig, c->nbar2, c->twx, c->twy,
+                  c->twx_d, c->twy_d, c->Mx, c->My, c->part, c->stats, c->sch, c->lam, c->trace};
+  for (void* p : bufs)
+    if (p) (void)hipFree(p);
+  if (c->h_ring) (void)hipHostFree(c->h_ring);
+  if (c->h_stats) (void)hipHostFree(c->h_stats);
+  for (auto& e : c->ev_ring)
+    if (e) (void)hipEventDestroy(e);
+  for (auto& e : c->prof_ev)
+    if (e) (void)hipEventDestroy(e);
+  delete c;
+}
+
+wf_status alloc(void** p, size_t bytes) {
+  hipError_t e = hipMalloc(p, bytes);
+  if (e != hipSuccess) {
+    *p = nullptr;
+    return from_hip(e);
+  }
+  return WF_OK;
+}
+
+wf_status create(const wf_shape* sh, Ctx** out) {
+  Ctx* c = new (std::nothrow) Ctx();
+  if (!c) return WF_ENOMEM;
+  c->ny = sh->ny;
+  c->nx = sh->nx;
+  c->prec = sh->precision;
+  c->esz = c->prec == WF_F64 ? 8 : 4;
+  c->nh = c->nx / 2 + 1;
+  c->kp = ((c->nh + kTC - 1) / kTC) * kTC;
+  c->kpm = ((c->nh + kTCM - 1) / kTCM) * kTCM;
+  (void)hipGetDevice(&c->device);
+  const size_t ny = c->ny, nx = c->nx, nh = c->nh, esz = c->esz;
+  const size_t modes = nh * ny;
+  wf_status st = WF_OK;
+#define A(ptr, bytes)                                 \
+  if ((st = alloc((void**)&(ptr), (bytes))) != WF_OK) { \
+    free_ctx(c);                                      \
+    return st;                                        \
+  }
+  A(c->B, ny * c->kp * 2 * esz);
+  A(c->tA, modes * 2 * esz);
+  A(c->dA, modes * 2 * esz);
+  A(c->tB, modes * 2 * esz);
+  A(c->sc, modes * esz);
+  A(c->nbA, modes * esz);
+  A(c->sy, modes * esz);
+  A(c->sig, modes * esz);
+  A(c->nbar2, ny * nx * esz);
+  A(c->twx, nx * 2 * esz);
+  A(c->twy, ny * 2 * esz);
+  A(c->twx_d, nx * sizeof(cx<double>));
+  A(c->twy_d, ny * sizeof(cx<double>));
+  A(c->Mx, ny * c->kpm * sizeof(cx<double>));
+  A(c->My, ny * c->kpm * sizeof(cx<double>));
+  const size_t npart = std::max<size_t>(2 * ny / kTRM, 16 * kStatBlocks);
+  A(c->part, npart * sizeof(double));
+  A(c->stats, 16 * sizeof(double));
+  A(c->sch, sizeof(DevSched));
+#undef A
+  hipError_t e = hipHostMalloc((void**)&c->h_ring, kRing * sizeof(DevSched), hipHostMallocDefault);
+  if (e == hipSuccess) e = hipHostMalloc((void**)&c->h_stats, 16 * sizeof(double), hipHostMallocDefault);
+  for (int i = 0; i < kRing && e == hipSuccess; ++i)
+    e = hipEventCreateWithFlags(&c->ev_ring[i], hipEventDisableTiming);
+  if (e != hipSuccess) {
+    free_ctx(c);
+    return from_hip(e);
+  }
+  // twiddle tables, computed in double and rounded once
+  std::vector<double> tdx, tdy;
+  make_table(tdx, c->nx);
+  make_table(tdy, c->ny);
+  e = hipMemcpy(c->twx_d, tdx.data(), tdx.size() * 8, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(c->twy_d, tdy.data(), tdy.size() * 8, hipMemcpyHostToDevice);
+  if (c->prec == WF_F64) {
+    if (e == hipSuccess) e = hipMemcpy(c->twx, tdx.data(), tdx.size() * 8, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(c->twy, tdy.data(), tdy.size() * 8, hipMemcpyHostToDevice);
+  } else {
+    std::vector<float> fx, fy;
+    make_table(fx, c->nx);
+    make_table(fy, c->ny);
+    if (e == hipSuccess) e = hipMemcpy(c->twx, fx.data(), fx.size() * 4, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(c->twy, fy.data(), fy.size() * 4, hipMemcpyHostToDevice);
+  }
+  if (e != hipSuccess) {
+    free_ctx(c);
+    return from_hip(e);
+  }
+  *out = c;
+  return WF_OK;
+}
+
+// ----- solve ---------------------------------------------------------------
+
+struct Chain {
+  int fk = FK_NONE;
+  double tauA = 0, tauB = 0, tauW = 0, cB = 0, phi = 0, tau_first = 0;
+  int n_levels = 1;
+  double tau_report[3] = {0, 0, 0};
+  PrepSpecArgs pa{};
+};
+
+wf_status plan_chain(const Ctx* c, const wf_schedule* s, bool has_oof, bool has_st,
+                     const double* pix, const double* spec, Chain* ch) {
+  const double min_npix = pix[1];
+  const double min_oof = spec[1];
+  const double min_nf = spec[2];  // min over modes of (P_1/f or 0) + nx P_st delta_kx0
+  const double b0 = s->beta[0], b1 = s->beta[1], b2 = s->beta[2];
+  const double alpha = s->floor_frac;
+  PrepSpecArgs& pa = ch->pa;
+  pa.ny = c->ny;
+  pa.nx = c->nx;
+  pa.has_oof = has_oof;
+  pa.has_st = has_st;
+  pa.sc_adds_nf = 0;
+  pa.nbA_kind = 0;
+  pa.phi_nf = 0.0;
+  pa.tauA = 0.0;
+  if (s->chain == WF_CHAIN_THREE) {
+    ch->phi = has_st ? alpha * min_npix : 0.0;
+    const double tau0 = has_oof ? b0 * min_oof : 0.0;
+    const double tau1 = has_st ? b1 * ch->phi : 0.0;
+    if (has_oof && !(tau0 > 0)) return WF_ENOTPD;
+    if (has_st && !(tau1 > 0)) return WF_ENOTPD;
+    ch->tau_report[0] = tau0;
+    ch->tau_report[1] = tau1;
+    if (has_oof && has_st) {
+      ch->fk = FK_ARRAY_STRIPE;
+      ch->tauA = tau0;
+      ch->tauB = tau1;
+      ch->n_levels = 3;
+    } else if (has_oof) {
+      ch->fk = FK_ARRAY;
+      ch->tauA = tau0;
+      ch->n_levels = 2;
+    } else if (has_st) {
+      ch->fk = FK_STRIPE;
+      ch->tauA = tau1;
+      ch->n_levels = 2;
+    }
+    ch->cB = ch->phi - tau1;
+    pa.nbA_kind = has_oof ? 1 : 0;
+    pa.tauA = tau0;
+  } else {
+    const bool any = has_oof || has_st;
+    ch->phi = (has_st && !has_oof) ? alpha * min_npix : 0.0;
+    pa.phi_nf = ch->phi;
+    if (s->chain == WF_CHAIN_MERGED && any) {
+      const double tauF = b0 * (min_nf + ch->phi);
+      if (!(tauF > 0)) return WF_ENOTPD;
+      ch->fk = FK_ARRAY;
+      ch->tauA = tauF;
+      ch->n_levels = 2;
+      ch->tau_report[0] = tauF;
+      pa.nbA_kind = 2;
+      pa.tauA = tauF;
+    } else if (s->chain == WF_CHAIN_AUGMENTED && any) {
+      pa.sc_adds_nf = 1;
+    }
+  }
+  ch->tauW = b2 * (min_npix - ch->phi);
+  if (!(ch->tauW > 0)) return WF_ENOTPD;
+  ch->tau_report[2] = ch->tauW;
+  ch->tau_first = ch->fk == FK_NONE ? ch->tauW : ch->tauA;
+  return WF_OK;
+}
+
+template <class T>
+SweepArgs<T> sweep_args(Ctx* c, const wf_inputs* in, const Chain& ch) {
+  SweepArgs<T> a{};
+  a.B = c->B;
+  a.tA = c->tA;
+  a.dA = c->dA;
+  a.tB = c->tB;
+  a.sc = (const T*)c->sc;
+  a.nbA = (const T*)c->nbA;
+  a.pst = in ? (const T*)in->p_stripe : nullptr;
+  a.d = in ? (const T*)in->d : nullptr;
+  a.nbar2 = (const T*)c->nbar2;
+  a.twx = c->twx;
+  a.twy = c->twy;
+  a.sch = c->sch;
+  a.lam = c->lam;
+  a.nx = c->nx;
+  a.ny = c->ny;
+  a.kp = c->kp;
+  a.fk = ch.fk;
+  a.tauA = ch.tauA;
+  a.tauB = ch.tauB;
+  a.tauW = ch.tauW;
+  a.cB = ch.cB;
+  a.scale = 1.0 / ((double)c->nx * (double)c->ny);
+  return a;
+}
+
+template <class T>
+MonArgs<T> mon_args(Ctx* c, const wf_inputs* in, const Chain& ch) {
+  MonArgs<T> m{};
+  m.tfirst = c->tA;
+  m.sc = (const T*)c->sc;
+  m.sy = (const T*)c->sy;
+  m.sig = (const T*)c->sig;
+  m.d = (const T*)in->d;
+  m.npix = (const T*)in->n_pix;
+  m.nbar2 = (const T*)c->nbar2;
+  m.Mx = c->Mx;
+  m.My = c->My;
+  m.twx = c->twx_d;
+  m.twy = c->twy_d;
+  m.sch = c->sch;
+  m.lam = c->lam;
+  m.part = c->part;
+  m.nx = c->nx;
+  m.ny = c->ny;
+  m.kpm = c->kpm;
+  m.tau_first = ch.tau_first;
+  m.scale = 1.0 / ((double)c->nx * (double)c->ny);
+  return m;
+}
+
+wf_status check_schedule(const wf_schedule* s) {
+  if (s->max_sweeps < 1 || s->monitor_every < 1) return WF_EINVAL;
+  if (s->kind == WF_SCHED_FIXED) {
+    if (!s->lambda || s->n_lambda < 1) return WF_EINVAL;
+    for (int i = 0; i < s->n_lambda; ++i)
+      if (!(s->lambda[i] > 0) || !std::isfinite(s->lambda[i])) return WF_EINVAL;
+  } else if (s->kind == WF_SCHED_ADAPTIVE) {
+    if (!(s->lambda0 >= 1.0) || !std::isfinite(s->lambda0)) return WF_EINVAL;
+    if (!(s->shrink_exp > 0 && s->shrink_exp < 1)) return WF_EINVAL;
+    if (!(s->plateau_rtol >= 0) || !(s->snap_eps >= 0)) return WF_EINVAL;
+  } else {
+    return WF_EINVAL;
+  }
+  if (!(s->rtol >= 0)) return WF_EINVAL;
+  for (int i = 0; i < 3; ++i)
+    if (!(s->beta[i] > 0 && s->beta[i] <= 1)) return WF_EINVAL;
+  if (!(s->floor_frac >= 0 && s->floor_frac < 1)) return WF_EINVAL;
+  if (s->chain < WF_CHAIN_THREE || s->chain > WF_CHAIN_AUGMENTED) return WF_EINVAL;
+  return WF_OK;
+}
+
+template <class T>
+wf_status solve_t(Ctx* c, const wf_inputs* in, const wf_schedule* s, const void* s_init,
+                  void* s_out, wf_report* rep, double* trace, hipStream_t st) {
+  const bool has_oof = in->p_oof != nullptr, has_st = in->p_stripe != nullptr;
+  // 1. validation statistics (one readback)
+  WF_TRY(launch_stats<T>((const T*)in->d, (const T*)in->n_pix, in->mask, (const T*)in->s_k,
+                         (const T*)in->p_oof, (const T*)in->p_stripe, c->ny, c->nx, c->part,
+                         kStatBlocks, c->stats, c->stats + 8, st));
+  WF_TRY(hipMemcpyAsync(c->h_stats, c->stats, 16 * sizeof(double), hipMemcpyDeviceToHost, st));
+  WF_TRY(hipStreamSynchronize(st));
+  double pix[8], spec[8];
+  std::memcpy(pix, c->h_stats, sizeof(pix));
+  std::memcpy(spec, c->h_stats + 8, sizeof(spec));
+  if (pix[0] < 1) return WF_EINVAL;                       // no observed pixel
+  if (pix[4] > 0) return WF_ENONFINITE;                   // NaN/Inf on observed pixels
+  if (spec[3] > 0 || spec[4] > 0 || spec[5] > 0) return WF_EINVAL;  // bad spectra
+  if (pix[5] > 0) return WF_ENOTPD;                       // N_pix <= 0 observed
+  Chain ch;
+  wf_status ps = plan_chain(c, s, has_oof, has_st, pix, spec, &ch);
+  if (ps != WF_OK) return ps;
+
+  // 2. coefficients
+  WF_TRY(launch_prep<T>((const T*)in->n_pix, in->mask, c->ny, c->nx, ch.phi + ch.tauW, (T*)c->nbar2,
+                        (const T*)in->s_k, (const T*)in->p_oof, (const T*)in->p_stripe, ch.pa,
+                        (T*)c->sc, (T*)c->nbA, (T*)c->sy, (T*)c->sig, st));
+
+  // 3. schedule on the device
+  const int K = s->monitor_every, maxs = s->max_sweeps;
+  const int n_chunks = (maxs + K - 1) / K;
+  if (c->lam_cap < maxs + 1) {
+    if (c->lam) (void)hipFree(c->lam);
+    c->lam = nullptr;
+    c->lam_cap = 0;
+    wf_status as = alloc((void**)&c->lam, (size_t)(maxs + 1) * sizeof(double));
+    if (as != WF_OK) return as;
+    c->lam_cap = maxs + 1;
+  }
+  if (c->trace_cap < n_chunks) {
+    if (c->trace) (void)hipFree(c->trace);
+    c->trace = nullptr;
+    c->trace_cap = 0;
+    wf_status as = alloc((void**)&c->trace, (size_t)n_chunks * 5 * sizeof(double));
+    if (as != WF_OK) return as;
+    c->trace_cap = n_chunks;
+  }
+  std::vector<double> lam(maxs + 1);
+  for (int k = 0; k <= maxs; ++k) {
+    if (s->kind == WF_SCHED_FIXED) lam[k] = s->lambda[std::min(k, s->n_lambda - 1)];
+    else lam[k] = s->lambda0;
+  }
+  DevSched h{};
+  h.base = 0;
+  h.done = 0;
+  h.status = WF_NOT_CONVERGED;
+  h.max_sweeps = maxs;
+  h.K = K;
+  h.adaptive = s->kind == WF_SCHED_ADAPTIVE;
+  h.max_rec = n_chunks;
+  h.stop_full = s->stop_full ? 1 : 0;
+  h.shrink = s->shrink_exp;
+  h.plateau = s->plateau_rtol;
+  h.snap = s->snap_eps;
+  h.rtol = s->rtol;
+  h.d2 = pix[3];
+  h.nu = pix[2];
+  WF_TRY(hipMemcpyAsync(c->lam, lam.data(), lam.size() * sizeof(double), hipMemcpyHostToDevice, st));
+  WF_TRY(hipMemcpyAsync(c->sch, &h, sizeof(h), hipMemcpyHostToDevice, st));
+
+  SweepArgs<T> a = sweep_args<T>(c, in, ch);
+  MonArgs<T> m = mon_args<T>(c, in, ch);
+
+  // 4. initial state
+  const size_t modes_b = (size_t)c->nh * c->ny * 2 * c->esz;
+  if (s_init) {
+    WF_TRY(launch_row<T>(ROW_R2C, a, 0, (const T*)s_init, nullptr, st));
+    WF_TRY(launch_col<T>(COL_INIT, a, 0, nullptr, lam[0], st));
+  } else {
+    WF_TRY(hipMemsetAsync(c->B, 0, (size_t)c->ny * c->kp * 2 * c->esz, st));
+    WF_TRY(hipMemsetAsync(c->tA, 0, modes_b, st));
+    WF_TRY(hipMemsetAsync(c->dA, 0, modes_b, st));
+    WF_TRY(hipMemsetAsync(c->tB, 0, modes_b, st));
+  }
+
+  // 5. sweeps
+  const bool prof = c->profiling != 0;
+  if (prof && (int)c->prof_ev.size() < kProfSlots) {
+    for (int i = (int)c->prof_ev.size(); i < kProfSlots; ++i) {
+      hipEvent_t e;
+      WF_TRY(hipEventCreate(&e));
+      c->prof_ev.push_back(e);
+    }
+  }
+  const int prof_chunks = kProfSlots / 5;
+  int launched = 0;
+  for (int ci = 0; ci < n_chunks; ++ci) {
+    const bool sample = prof && ci < prof_chunks;
+    hipEvent_t* ev = sample ? &c->prof_ev[5 * ci] : nullptr;
+    for (int k = 0; k < K; ++k) {
+      if (sample && k == 0) WF_TRY(hipEventRecord(ev[0], st));
+      WF_TRY(launch_row<T>(ROW_SWEEP, a, k, nullptr, nullptr, st));
+      if (sample && k == 0) WF_TRY(hipEventRecord(ev[1], st));
+      WF_TRY(launch_col<T>(COL_SWEEP, a, k, nullptr, 0.0, st));
+      if (sample && k == 0) WF_TRY(hipEventRecord(ev[2], st));
+    }
+    if (sample) WF_TRY(hipEventRecord(ev[3], st));
+    WF_TRY(launch_mon_col<T>(m, MON_RESIDUAL, 0.0, st));
+    WF_TRY(launch_mon_row<T>(m, MON_RESIDUAL, nullptr, st));
+    WF_TRY(launch_controller(c->sch, c->lam, c->part, c->ny / kTRM, c->trace, st));
+    if (sample) WF_TRY(hipEventRecord(ev[4], st));
+    const int slot = ci % kRing;
+    WF_TRY(hipMemcpyAsync(&c->h_ring[slot], c->sch, sizeof(DevSched), hipMemcpyDeviceToHost, st));
+    WF_TRY(hipEventRecord(c->ev_ring[slot], st));
+    launched = ci + 1;
+    if (ci >= kLag) {
+      const int chk = (ci - kLag) % kRing;
+      WF_TRY(hipEventSynchronize(c->ev_ring[chk]));
+      if (c->h_ring[chk].done) break;
+    }
+  }
+  WF_TRY(hipStreamSynchronize(st));
+  DevSched fin;
+  WF_TRY(hipMemcpy(&fin, c->sch, sizeof(fin), hipMemcpyDeviceToHost));
+
+  // 6. output s = S x, x = t_A / (S_chain + T_A) at the last lambda
+  WF_TRY(launch_mon_col<T>(m, MON_OUTPUT, fin.lam_last, st));
+  WF_TRY(launch_mon_row<T>(m, MON_OUTPUT, (T*)s_out, st));
+  if (trace && fin.n_rec > 0)
+    WF_TRY(hipMemcpyAsync(trace, c->trace, (size_t)fin.n_rec * 5 * sizeof(double),
+                          hipMemcpyDeviceToHost, st));
+  WF_TRY(hipStreamSynchronize(st));
+
+  if (rep) {
+    std::memset(rep, 0, sizeof(*rep));
+    rep->status = fin.status;
+    rep->sweeps = fin.sweeps_done;
+    rep->n_records = fin.n_rec;
+    rep->n_levels = ch.n_levels;
+    rep->lambda = fin.lam_last;
+    rep->rho = fin.rho;
+    rep->rho_mask = fin.rho_mask;
+    rep->dd2 = fin.dd2;
+    rep->d2 = pix[3];
+    for (int i = 0; i < 3; ++i) rep->tau[i] = ch.tau_report[i];
+    rep->phi = ch.phi;
+    if (prof) {
+      const int last_chunk = fin.sweeps_done > 0 ? (fin.sweeps_done - 1) / K : 0;
+      const int nsamp = std::min(std::min(launched, prof_chunks), last_chunk + 1);
+      for (int ci = 0; ci < nsamp; ++ci) {
+        hipEvent_t* ev = &c->prof_ev[5 * ci];
+        float t01 = 0, t12 = 0, t34 = 0;
+        WF_TRY(hipEventElapsedTime(&t01, ev[0], ev[1]));
+        WF_TRY(hipEventElapsedTime(&t12, ev[1], ev[2]));
+        WF_TRY(hipEventElapsedTime(&t34, ev[3], ev[4]));
+        rep->kernel_ms[0] += t01;
+        rep->kernel_ms[1] += t12;
+        rep->kernel_ms[2] += t34;
+        rep->kernel_launches[0] += 1;
+        rep->kernel_launches[1] += 1;
+        rep->kernel_launches[2] += 1;
+      }
+    }
+  }
+  return (wf_status)fin.status;
+}
+
+template <class T>
+wf_status fft_t(Ctx* c, const void* src, void* dst, bool forward, hipStream_t st) {
+  Chain ch;
+  SweepArgs<T> a = sweep_args<T>(c, nullptr, ch);
+  if (forward) {
+    WF_TRY(launch_row<T>(ROW_R2C, a, 0, (const T*)src, nullptr, st));
+    WF_TRY(launch_col<T>(COL_FWD_OUT, a, 0, dst, 0.0, st));
+  } else {
+    WF_TRY(launch_col<T>(COL_INV_IN, a, 0, const_cast<void*>(src), 0.0, st));
+    WF_TRY(launch_row<T>(ROW_C2R, a, 0, nullptr, (T*)dst, st));
+  }
+  WF_TRY(hipStreamSynchronize(st));
+  return WF_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+wf_status wf_ctx_create(const wf_shape* shape, void** out) {
+  if (!shape || !out) return WF_EINVAL;
+  *out = nullptr;
+  if (shape->precision != WF_F32 && shape->precision != WF_F64) return WF_EINVAL;
+  if (!supported(shape->ny, shape->nx, shape->precision)) return WF_EUNSUPPORTED;
+  Ctx* c = nullptr;
+  wf_status s = create(shape, &c);
+  if (s == WF_OK) *out = c;
+  return s;
+}
+
+void wf_ctx_destroy(void* ctx) {
+  if (ctx) free_ctx((Ctx*)ctx);
+}
+
+void wf_schedule_default(wf_schedule* s) {
+  if (!s) return;
+  std::memset(s, 0, sizeof(*s));
+  s->kind = WF_SCHED_ADAPTIVE;
+  s->lambda0 = 1.0e4;
+  s->shrink_exp = 0.7;
+  s->plateau_rtol = 1.0e-2;
+  s->snap_eps = 1.0e-3;
+  s->rtol = 1.0e-6;
+  s->max_sweeps = 20000;
+  s->monitor_every = 16;
+  s->beta[0] = 0.9;
+  s->beta[1] = 0.9;
+  s->beta[2] = 1.0;
+  s->floor_frac = 0.5;
+  s->chain = WF_CHAIN_THREE;
+  s->stop_full = 0;
+}
+
+wf_status wf_solve(void* ctx, const wf_inputs* in, const wf_schedule* sch, const void* s_init,
+                   void* s_out, wf_report* rep, double* trace, hipStream_t stream) {
+  Ctx* c = (Ctx*)ctx;
+  if (!c || !in || !sch || !s_out || !in->d || !in->s_k || !in->n_pix) return WF_EINVAL;
+  wf_status v = check_schedule(sch);
+  if (v != WF_OK) return v;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev != c->device) return WF_EINVAL;
+  if (c->prec == WF_F64) return solve_t<double>(c, in, sch, s_init, s_out, rep, trace, stream);
+  return solve_t<float>(c, in, sch, s_init, s_out, rep, trace, stream);
+}
+
+wf_status wf_rfft2(void* ctx, const void* x, void* X, hipStream_t stream) {
+  Ctx* c = (Ctx*)ctx;
+  if (!c || !x || !X) return WF_EINVAL;
+  if (c->prec == WF_F64) return fft_t<double>(c, x, X, true, stream);
+  return fft_t<float>(c, x, X, true, stream);
+}
+
+wf_status wf_irfft2(void* ctx, const void* X, void* x, hipStream_t stream) {
+  Ctx* c = (Ctx*)ctx;
+  if (!c || !x || !X) return WF_EINVAL;
+  if (c->prec == WF_F64) return fft_t<double>(c, X, x, false, stream);
+  return fft_t<float>(c, X, x, false, stream);
+}
+
+wf_status wf_ctx_set_profiling(void* ctx, int32_t enable) {
+  Ctx* c = (Ctx*)ctx;
+  if (!c) return WF_EINVAL;
+  c->profiling = enable ? 1 : 0;
+  return WF_OK;
+}
+
+int32_t wf_supported(int32_t ny, int32_t nx, int32_t precision) { return supported(ny, nx, precision); }
+
+const char* wf_strerror(int32_t s) {
+  switch (s) {
+    case WF_OK: return "ok";
+    case WF_NOT_CONVERGED: return "sweep budget exhausted before the residual target";
+    case WF_EINVAL: return "invalid argument";
+    case WF_ENOTPD: return "a messenger covariance tau_i is not positive (empty noise term)";
+    case WF_ENONFINITE: return "non-finite value in the inputs or the iteration";
+    case WF_EDEVICE: return "HIP runtime error";
+    case WF_ENOMEM: return "device allocation failed";
+    case WF_EUNSUPPORTED: return "map size or precision not supported";
+    default: return "unknown status";
+  }
+}
+
+}  // extern "C"

@@ -1,0 +1,74 @@
+"""The C-ABI library loads and exports what include/wf.h declares (CPU only:
+no compute call is made)."""
+
+import ctypes
+import os
+import re
+import shutil
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "wf.h")
+LIB = os.path.join(ROOT, "paper_1704_00865_amd", "libwf.so")
+
+
+def _declared():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(wf_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_header_declares_the_boundary():
+    names = _declared()
+    for required in ("wf_ctx_create", "wf_ctx_destroy", "wf_solve", "wf_strerror"):
+        assert required in names
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libwf.so not built")
+def test_library_exports_every_declared_symbol():
+    lib = ctypes.CDLL(LIB)
+    missing = [n for n in _declared() if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libwf.so not built")
+def test_binding_declares_every_export():
+    import paper_1704_00865_amd as wf
+    assert sorted(wf.EXPORTS) == _declared()
+    wf.load()
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libwf.so not built")
+def test_host_only_calls():
+    import paper_1704_00865_amd as wf
+    lib = wf.load()
+    assert lib.wf_supported(2048, 2048, 0) == 1
+    assert lib.wf_supported(4096, 4096, 0) == 1
+    assert lib.wf_supported(4096, 4096, 1) == 0
+    assert lib.wf_supported(100, 128, 0) == 0
+    assert lib.wf_supported(32, 64, 0) == 0
+    s = wf._Schedule()
+    lib.wf_schedule_default(ctypes.byref(s))
+    assert s.kind == 1 and s.lambda0 == 1.0e4 and s.shrink_exp == 0.7
+    assert list(s.beta) == [0.9, 0.9, 1.0] and s.chain == 0
+    for code in (0, 1, -1, -2, -3, -4, -5, -6):
+        assert wf.strerror(code)
+
+
+@pytest.mark.skipif(shutil.which("gcc") is None, reason="no gcc")
+def test_ctypes_layout_matches_c_structs(tmp_path):
+    import paper_1704_00865_amd as wf
+    src = tmp_path / "sz.c"
+    src.write_text('#include <stdio.h>\n#include <stddef.h>\n#include "wf.h"\n'
+                   "int main(void){printf(\"%zu %zu %zu %zu %zu %zu\\n\", sizeof(wf_schedule),"
+                   " sizeof(wf_report), sizeof(wf_inputs), sizeof(wf_shape),"
+                   " offsetof(wf_schedule, chain), offsetof(wf_report, kernel_ms));return 0;}\n")
+    exe = tmp_path / "sz"
+    subprocess.check_call(["gcc", "-D__HIP_PLATFORM_AMD__", "-I", os.path.join(ROOT, "include"),
+                           "-I", "/opt/rocm/include", str(src), "-o", str(exe)])
+    got = [int(v) for v in subprocess.check_output([str(exe)]).split()]
+    assert got == [ctypes.sizeof(wf._Schedule), ctypes.sizeof(wf._Report),
+                   ctypes.sizeof(wf._Inputs), ctypes.sizeof(wf._Shape),
+                   wf._Schedule.chain.offset, wf._Report.kernel_ms.offset]

@@ -1,0 +1,245 @@
+"""GPU messenger iteration against the CPU float64 oracle on identical inputs.
+
+Iterate parity: both sides run the same fixed lambda sequence for the same
+number of sweeps and the signal estimates are compared element by element
+(relative L2): <= 1e-10 for the float64 path, <= 1e-5 for the float32 path.
+"""
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"f32": 1e-5, "f64": 1e-10}
+
+
+def _tensors(p, prec, device="cuda"):
+    import torch
+    dt = torch.float32 if prec == "f32" else torch.float64
+
+    def t(a):
+        return None if a is None else torch.tensor(np.ascontiguousarray(a), dtype=dt, device=device)
+    mask = None if p.mask is None else torch.tensor(p.mask, dtype=torch.uint8, device=device)
+    return t(p.d), t(p.s_k), t(p.n_pix), t(p.p_oof), t(p.p_stripe), mask
+
+
+def _run_both(gpu_lib, p, prec, lams, *, chain="three", beta=(0.9, 0.9, 1.0), floor_frac=0.5,
+              monitor_every=8, s_init=None):
+    import torch
+    ny, nx = p.d.shape
+    print(f"parity {prec} {ny}x{nx} chain={chain} sweeps={len(lams)} "
+          f"mask={p.mask is not None} oof={p.p_oof is not None} "
+          f"stripe={p.p_stripe is not None} warm={s_init is not None}", flush=True)
+    ctx = gpu_lib.Context(ny, nx, prec)
+    sched = gpu_lib.Schedule(lambdas=list(lams), rtol=0.0, max_sweeps=len(lams),
+                             monitor_every=monitor_every, beta=beta, floor_frac=floor_frac,
+                             chain=chain)
+    args = _tensors(p, prec)
+    si = None
+    if s_init is not None:
+        si = torch.tensor(s_init, dtype=args[0].dtype, device="cuda")
+    s_gpu, rep, trace = ctx.solve(*args, schedule=sched, s_init=si)
+    s_gpu = s_gpu.cpu().numpy().astype(np.float64)
+    si_np = None if si is None else si.cpu().numpy().astype(np.float64)
+    res = oracle.solve(p, oracle.FixedSchedule(list(lams)),
+                       settings=oracle.Settings(beta=beta, floor_frac=floor_frac, chain=chain),
+                       s_init=si_np, max_sweeps=len(lams), monitor_every=monitor_every)
+    return s_gpu, rep, trace, res
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def _ramp(n_cool, n, lam0=1e3):
+    return oracle.cooling_ramp(n_cool, n, lam0)
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+@pytest.mark.parametrize("chain", ["three", "merged", "augmented"])
+def test_iterate_parity_c1_shape(gpu_lib, prec, chain):
+    p = synth.make_problem(64, 64, 1)
+    s_gpu, rep, trace, res = _run_both(gpu_lib, p, prec, _ramp(40, 60), chain=chain)
+    assert rep["sweeps"] == 60 and rep["status"] == "NOT_CONVERGED"
+    assert _rel(s_gpu, res.s) < TOL[prec]
+    # monitor trace: same sweeps, lambdas and residuals
+    assert trace.shape[0] == len(res.trace)
+    for g, o in zip(trace, res.trace):
+        assert g[0] == o[0] and g[1] == o[1]
+        rt = 1e-8 if prec == "f64" else 2e-3
+        assert g[2] == pytest.approx(o[2], rel=rt)
+        assert g[4] == pytest.approx(o[4], rel=rt, abs=1e-12)
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+@pytest.mark.parametrize("shape", [(128, 64), (64, 256), (256, 256)])
+def test_iterate_parity_masked_nonsquare(gpu_lib, prec, shape):
+    ny, nx = shape
+    p = synth.make_problem(ny, nx, 21, mask_frac=0.08)
+    s_gpu, rep, trace, res = _run_both(gpu_lib, p, prec, _ramp(20, 40), monitor_every=16)
+    assert _rel(s_gpu, res.s) < TOL[prec]
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+@pytest.mark.parametrize("terms", [("oof",), ("stripe",), (), ("oof", "stripe")])
+@pytest.mark.parametrize("chain", ["three", "merged", "augmented"])
+def test_iterate_parity_term_subsets(gpu_lib, prec, terms, chain):
+    p = synth.make_problem(64, 128, 5, mask_frac=0.05,
+                           oof_level=10.0 if "oof" in terms else None,
+                           stripe_rms=10.0 if "stripe" in terms else None)
+    s_gpu, rep, trace, res = _run_both(gpu_lib, p, prec, _ramp(12, 24), chain=chain,
+                                       monitor_every=5)
+    assert _rel(s_gpu, res.s) < TOL[prec]
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+@pytest.mark.parametrize("chain", ["three", "augmented"])
+def test_warm_start_parity(gpu_lib, prec, chain):
+    p = synth.make_problem(64, 64, 9, mask_frac=0.1)
+    s_init = np.asarray(p.s_true, dtype=np.float32 if prec == "f32" else np.float64)
+    s_gpu, rep, trace, res = _run_both(gpu_lib, p, prec, _ramp(10, 20, 50.0), chain=chain,
+                                       s_init=s_init)
+    assert _rel(s_gpu, res.s) < TOL[prec]
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_single_sweep_and_ragged_chunk(gpu_lib, prec):
+    """max_sweeps = 1, and a budget that is not a multiple of the monitor
+    interval (the last chunk is partial)."""
+    p = synth.make_problem(64, 64, 2)
+    for lams, K in (([30.0], 4), (list(_ramp(7, 13, 100.0)), 5)):
+        s_gpu, rep, trace, res = _run_both(gpu_lib, p, prec, lams, monitor_every=K)
+        assert rep["sweeps"] == len(lams)
+        assert _rel(s_gpu, res.s) < TOL[prec]
+        assert trace[-1][0] == len(lams) - 1
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_adaptive_schedule_replayed_by_oracle(gpu_lib, prec):
+    """The adaptive lambda trajectory depends on rounding, so the oracle
+    replays the lambdas the GPU recorded (constant within a monitor chunk)."""
+    import torch  # noqa: F401
+    p = synth.make_problem(64, 64, 4)
+    ctx = gpu_lib.Context(64, 64, prec)
+    K = 4
+    sched = gpu_lib.Schedule(lambda0=1e3, rtol=0.0, max_sweeps=80, monitor_every=K,
+                             chain="augmented")
+    s_gpu, rep, trace = ctx.solve(*_tensors(p, prec), schedule=sched)
+    lams = np.repeat(trace[:, 1], K)[: rep["sweeps"]]
+    assert trace[0, 1] == 1e3 and lams[-1] < 1e3  # it did cool
+    res = oracle.solve(p, oracle.FixedSchedule(list(lams)),
+                       settings=oracle.Settings(chain="augmented"), max_sweeps=len(lams),
+                       monitor_every=K)
+    assert _rel(s_gpu.cpu().numpy().astype(np.float64), res.s) < TOL[prec]
+
+
+def test_converges_to_dense_wiener_solution_f64(gpu_lib):
+    """C1 workload (64x64, three terms) on the float64 path with the
+    augmented chain, run to rho <= 1e-12 and compared with the dense
+    4096x4096 Cholesky solve."""
+    from oracle import direct
+    p = synth.named_config("c1")
+    ctx = gpu_lib.Context(64, 64, "f64")
+    sched = gpu_lib.Schedule(lambda0=1e4, rtol=1e-12, max_sweeps=5000, monitor_every=4,
+                             chain="augmented")
+    s_gpu, rep, trace = ctx.solve(*_tensors(p, "f64"), schedule=sched)
+    assert rep["status"] == "OK"
+    sd = direct.wiener_dense(p)
+    assert _rel(s_gpu.cpu().numpy(), sd) < 1e-10
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_stationary_closed_form_one_sweep(gpu_lib, prec):
+    """Uniform white noise with beta_white = 1 and the augmented chain: the
+    single messenger takes all the pixel noise and one sweep at lambda = 1 is
+    the exact per-mode filter (Section 3.1), at a bench-sized map."""
+    from oracle import direct
+    n = 1024 if prec == "f64" else 2048
+    p = synth.make_stationary_problem(n, n, 8)
+    ctx = gpu_lib.Context(n, n, prec)
+    sched = gpu_lib.Schedule(lambdas=[1.0], rtol=0.0, max_sweeps=1, monitor_every=1,
+                             chain="augmented")
+    s_gpu, rep, trace = ctx.solve(*_tensors(p, prec), schedule=sched)
+    sc = direct.wiener_stationary(p)
+    assert _rel(s_gpu.cpu().numpy().astype(np.float64), sc) < TOL[prec]
+    assert rep["rho"] < (1e-12 if prec == "f64" else 1e-5)
+
+
+def test_full_size_iterate_parity_c3(gpu_lib):
+    """The 2048x2048 masked workload in the launch configuration the
+    benchmark times (float32, three levels): a few sweeps against the oracle."""
+    oracle.bases.set_workers(16)
+    p = synth.named_config("c3")
+    lams = [1e4, 5e3, 2e3, 1e3]
+    s_gpu, rep, trace, res = _run_both(gpu_lib, p, "f32", lams, monitor_every=2)
+    assert _rel(s_gpu, res.s) < TOL["f32"]
+    for g, o in zip(trace, res.trace):
+        assert g[2] == pytest.approx(o[2], rel=2e-3)
+
+
+# ---------------------------------------------------------------------------
+# error handling
+# ---------------------------------------------------------------------------
+
+def _expect(gpu_lib, status, p, prec="f32", **kw):
+    ctx = gpu_lib.Context(*p.d.shape, prec)
+    sched = gpu_lib.Schedule(lambdas=[10.0, 1.0], rtol=0.0, max_sweeps=4, monitor_every=2, **kw)
+    with pytest.raises(gpu_lib.WFError) as ei:
+        ctx.solve(*_tensors(p, prec), schedule=sched)
+    assert gpu_lib.STATUS[ei.value.status] == status
+
+
+def test_error_codes(gpu_lib):
+    p = synth.make_problem(64, 64, 1)
+    q = synth.make_problem(64, 64, 1)
+    q.d = q.d.copy()
+    q.d[3, 4] = np.nan
+    _expect(gpu_lib, "ENONFINITE", q)
+    q = synth.make_problem(64, 64, 1)
+    q.p_oof = np.zeros_like(q.p_oof)
+    _expect(gpu_lib, "ENOTPD", q)
+    q = synth.make_problem(64, 64, 1)
+    q.mask = np.zeros((64, 64), np.uint8)
+    _expect(gpu_lib, "EINVAL", q)
+    _expect(gpu_lib, "ENOTPD", p, floor_frac=0.0)
+    q = synth.make_problem(64, 64, 1)
+    q.n_pix = q.n_pix.copy()
+    q.n_pix[0, 0] = -1.0
+    _expect(gpu_lib, "ENOTPD", q)
+    q = synth.make_problem(64, 64, 1)
+    q.s_k = q.s_k.copy()
+    q.s_k[1, 1] = -1.0
+    _expect(gpu_lib, "EINVAL", q)
+    ctx = gpu_lib.Context(64, 64, "f32")
+    with pytest.raises(gpu_lib.WFError):
+        ctx.solve(*_tensors(p, "f32"), schedule=gpu_lib.Schedule(max_sweeps=0))
+    with pytest.raises(gpu_lib.WFError) as ei:
+        gpu_lib.Context(100, 64, "f32")
+    assert gpu_lib.STATUS[ei.value.status] == "EUNSUPPORTED"
+
+
+def test_masked_pixel_values_are_ignored(gpu_lib):
+    p = synth.make_problem(64, 64, 6, mask_frac=0.1)
+    ctx = gpu_lib.Context(64, 64, "f32")
+    sched = gpu_lib.Schedule(lambdas=list(_ramp(10, 20)), rtol=0.0, max_sweeps=20, monitor_every=5)
+    a, _, _ = ctx.solve(*_tensors(p, "f32"), schedule=sched)
+    a = a.cpu().numpy().copy()
+    q = synth.make_problem(64, 64, 6, mask_frac=0.1)
+    q.d = np.where(q.mask == 0, np.nan, q.d)
+    q.n_pix = np.where(q.mask == 0, -3.0, q.n_pix)
+    b, _, _ = ctx.solve(*_tensors(q, "f32"), schedule=sched)
+    np.testing.assert_array_equal(a, b.cpu().numpy())
+
+
+def test_bitwise_deterministic(gpu_lib):
+    p = synth.make_problem(256, 256, 3, mask_frac=0.1)
+    ctx = gpu_lib.Context(256, 256, "f32")
+    sched = gpu_lib.Schedule(lambda0=1e3, rtol=0.0, max_sweeps=64, monitor_every=8)
+    a, ra, ta = ctx.solve(*_tensors(p, "f32"), schedule=sched)
+    a = a.cpu().numpy().copy()
+    b, rb, tb = ctx.solve(*_tensors(p, "f32"), schedule=sched)
+    np.testing.assert_array_equal(a, b.cpu().numpy())
+    np.testing.assert_array_equal(ta, tb)
