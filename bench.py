@@ -1,0 +1,234 @@
+"""Benchmark: multi-messenger Wiener filter on one MI355X.
+
+Workload: a 2048x2048 periodic map (4.19 M pixels, 2' pixels) with all three
+noise terms (1/f, row stripes, inhomogeneous white) and 10% of the pixels
+masked by random discs; inputs are seeded synthetic draws resident in HBM.
+
+One step = one complete wf_solve of that map with the three-level chain in
+float32 (setup, 500 sweeps of the fixed cooling schedule lambda_k =
+1e4^(1 - k/400) then 1, float64 residual monitor every 16 sweeps, output).
+value = sweeps / second over the timed steps (map-sweeps/s).
+
+Also printed, on the same JSON line:
+  roofline      the dominant kernel (column pass), algorithmic bytes per launch
+                / its mean duration from HIP events on the solve stream
+  time_to_rtol  wall time of a zero-start solve to rho <= 1e-6 with the
+                augmented chain (the only chain that reaches it at this size)
+  cpu_baseline  the float64 CPU oracle on a bounded sample of sweeps
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def _args():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--size", type=int, default=2048)
+    ap.add_argument("--sweeps", type=int, default=500)
+    ap.add_argument("--monitor-every", type=int, default=16)
+    ap.add_argument("--chain", default="three")
+    ap.add_argument("--skip-cpu", action="store_true")
+    ap.add_argument("--skip-ttr", action="store_true")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="also run a plain 1 GiB device copy (counter calibration)")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--tile", type=int, default=-1,
+                    help="transit-buffer tiling; -1 = autotune over the built ones")
+    return ap.parse_args()
+
+
+def column_bytes(ny, nx, esz=4):
+    """Algorithmic HBM bytes of one column-kernel launch (three-level chain):
+    transit buffer read + write, t_1, d_0, t_0 read + write (complex), S and
+    Nbar_0 read (real), stripe spectrum (one value per row)."""
+    nh = nx // 2 + 1
+    cpx = 2 * esz
+    return ny * nh * (2 * cpx + 6 * cpx + 2 * esz) + ny * esz
+
+
+def row_bytes(ny, nx, esz=4):
+    """Row-kernel launch: d and Nbar_2 read, transit buffer read + write."""
+    nh = nx // 2 + 1
+    return ny * nx * 2 * esz + ny * nh * 2 * 2 * esz
+
+
+def main():
+    a = _args()
+    if a.gpus != 1:
+        print(f"bench.py runs on one GPU; --gpus {a.gpus} is not supported "
+              "(independent maps shard by map, see the design notes)", file=sys.stderr)
+        sys.exit(2)
+    import torch
+
+    import oracle
+    import paper_1704_00865_amd as wf
+    import synth
+
+    wf.load()
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    n = a.size
+    print(f"[bench] generating {n}x{n} inputs", file=sys.stderr, flush=True)
+    p = synth.make_problem(n, n, 3, mask_frac=0.10)
+
+    def t(x):
+        return torch.tensor(np.ascontiguousarray(x), dtype=torch.float32, device=dev)
+    args = (t(p.d), t(p.s_k), t(p.n_pix), t(p.p_oof), t(p.p_stripe),
+            torch.tensor(p.mask, dtype=torch.uint8, device=dev))
+    out = torch.empty((n, n), dtype=torch.float32, device=dev)
+    ctx = wf.Context(n, n, "f32", device=dev)
+    lams = list(oracle.cooling_ramp(400, a.sweeps, 1.0e4)) if a.sweeps > 400 else \
+        list(oracle.cooling_ramp(a.sweeps * 4 // 5, a.sweeps, 1.0e4))
+    sched = wf.Schedule(lambdas=lams, rtol=0.0, max_sweeps=a.sweeps,
+                        monitor_every=a.monitor_every, chain=a.chain)
+
+    if a.copy_probe:
+        src = torch.empty(256 * 1024 * 1024, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        src.fill_(1.0)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print(f"[bench] copy probe: {src.numel() * 4} bytes read, {dst.numel() * 4} written",
+              file=sys.stderr, flush=True)
+        del src, dst
+
+    tile_times = {}
+    if a.tile >= 0:
+        if not ctx.set_tile(a.tile):
+            raise SystemExit(f"tiling {a.tile} is not built for {n}x{n}")
+    else:
+        # autotune: time a short solve with every tiling built for this size
+        probe = wf.Schedule(lambdas=lams[:48], rtol=0.0, max_sweeps=48,
+                            monitor_every=a.monitor_every, chain=a.chain)
+        for tile in range(wf.load().wf_tile_count()):
+            if not ctx.set_tile(tile):
+                continue
+            ctx.solve(*args, schedule=probe, out=out)
+            torch.cuda.synchronize()
+            tt = time.perf_counter()
+            for _ in range(2):
+                ctx.solve(*args, schedule=probe, out=out)
+            torch.cuda.synchronize()
+            tile_times[tile] = (time.perf_counter() - tt) / 2
+            print(f"[bench] tiling {tile}: {1e3 * tile_times[tile]:.2f} ms / 48 sweeps",
+                  file=sys.stderr, flush=True)
+        ctx.set_tile(min(tile_times, key=tile_times.get))
+    for i in range(a.warmup):
+        ctx.solve(*args, schedule=sched, out=out)
+        print(f"[bench] warmup {i + 1}/{a.warmup} done", file=sys.stderr, flush=True)
+    ctx.set_profiling(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sweeps = 0
+    kms = np.zeros(4)
+    kn = np.zeros(4)
+    rep = None
+    for i in range(a.steps):
+        _, rep, trace = ctx.solve(*args, schedule=sched, out=out)
+        sweeps += rep["sweeps"]
+        kms += rep["kernel_ms"]
+        kn += rep["kernel_launches"]
+        print(f"[bench] step {i + 1}/{a.steps}: {rep['sweeps']} sweeps, rho {rep['rho']:.3e}",
+              file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    ctx.set_profiling(False)
+    ms_step = 1e3 * dt / a.steps
+    value = sweeps / dt
+
+    col_ms = kms[1] / max(kn[1], 1)
+    row_ms = kms[0] / max(kn[0], 1)
+    cb = column_bytes(n, n)
+    achieved = cb / (col_ms * 1e-3) / 1e9
+    roof = {"bound": "hbm", "kernel": "col_kernel<float,%d,SWEEP>" % n,
+            "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+            "bytes_per_launch": cb, "mean_launch_us": round(col_ms * 1e3, 2),
+            "row_kernel": {"bytes_per_launch": row_bytes(n, n),
+                           "mean_launch_us": round(row_ms * 1e3, 2),
+                           "achieved": round(row_bytes(n, n) / (row_ms * 1e-3) / 1e9, 1)},
+            "sweep_bytes": cb + row_bytes(n, n)}
+
+    ttr = None
+    if not a.skip_ttr:
+        s2 = wf.Schedule(lambda0=1.0e4, rtol=1e-6, max_sweeps=60000, monitor_every=16,
+                         chain="augmented")
+        ctx.solve(*args, schedule=s2, out=out)  # warm
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        _, r2, _ = ctx.solve(*args, schedule=s2, out=out)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter() - t1
+        ttr = {"chain": "augmented", "rtol": 1e-6, "status": r2["status"],
+               "sweeps": r2["sweeps"], "seconds": round(t2, 4), "rho": r2["rho"],
+               "rho_mask": r2["rho_mask"],
+               "map_sweeps_per_s": round(r2["sweeps"] / t2, 1)}
+        print(f"[bench] time-to-1e-6 (augmented): {t2:.3f}s, {r2['sweeps']} sweeps, "
+              f"{r2['status']}", file=sys.stderr, flush=True)
+
+    cpu = None
+    if not a.skip_cpu:
+        cores = min(16, os.cpu_count() or 1)
+        oracle.bases.set_workers(cores)
+        st = oracle.setup(p, oracle.Settings(chain=a.chain))
+        x = oracle.init_state(st, lams[0])
+        tc = time.perf_counter()
+        k = 0
+        while True:
+            oracle.sweep(st, x, lams[min(k, len(lams) - 1)])
+            k += 1
+            if time.perf_counter() - tc > a.cpu_seconds:
+                break
+        tcpu = time.perf_counter() - tc
+        cpu = {"value": round(k / tcpu, 4), "unit": "map-sweeps/s", "cores": cores,
+               "kind": "oracle",
+               "sample": f"{k} float64 sweeps of the same {n}x{n} three-level problem "
+                         f"({tcpu:.1f} s, scipy.fft workers={cores}); setup and monitor excluded"}
+        print(f"[bench] cpu oracle: {k} sweeps in {tcpu:.1f}s", file=sys.stderr, flush=True)
+
+    line = {
+        "metric": "map-sweeps/s",
+        "value": round(value, 1),
+        "unit": "map-sweeps/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": round(ms_step, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"{n}x{n} map, 1/f + stripe + inhomogeneous white noise, "
+                               f"10% disc mask; {a.chain} chain, {a.sweeps}-sweep fixed "
+                               f"cooling schedule, monitor every {a.monitor_every}",
+                   "map": [n, n], "sweeps_per_step": a.sweeps, "chain": a.chain,
+                   "seed": 3, "tiling": ctx.tile,
+                   "tiling_ms_per_48_sweeps": {str(k): round(1e3 * v, 3)
+                                               for k, v in tile_times.items()}},
+        "roofline": roof,
+        "time_to_rtol": ttr,
+        "cpu_baseline": cpu,
+        "final_rho": rep["rho"] if rep else None,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -151,6 +151,14 @@ wf_status wf_irfft2(void* ctx, const void* X, void* x, hipStream_t stream);
 /* Turn per-kernel timing with HIP events on the solve stream on (1) or off. */
 wf_status wf_ctx_set_profiling(void* ctx, int32_t enable);
 
+/* Transit-buffer tilings (rows x columns per tile, rows per row block) the
+ * library holds, and the one a context uses.  Only tiling 0..count-1 exist;
+ * wf_ctx_set_tile returns WF_EUNSUPPORTED for a tiling not built for the
+ * context's size and precision.  An autotuner times the candidates. */
+int32_t wf_tile_count(void);
+wf_status wf_ctx_set_tile(void* ctx, int32_t tile);
+int32_t wf_ctx_get_tile(void* ctx);
+
 /* Sizes the library was built for, and its precision support. */
 int32_t wf_supported(int32_t ny, int32_t nx, int32_t precision);
 

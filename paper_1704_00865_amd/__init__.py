@@ -66,7 +66,8 @@ class _Report(ctypes.Structure):
 
 
 EXPORTS = ("wf_ctx_create", "wf_ctx_destroy", "wf_schedule_default", "wf_solve", "wf_rfft2",
-           "wf_irfft2", "wf_ctx_set_profiling", "wf_supported", "wf_strerror")
+           "wf_irfft2", "wf_ctx_set_profiling", "wf_supported", "wf_strerror", "wf_tile_count",
+           "wf_ctx_set_tile", "wf_ctx_get_tile")
 
 
 def load():
@@ -97,6 +98,12 @@ def load():
     lib.wf_ctx_set_profiling.restype = i32
     lib.wf_supported.argtypes = [i32, i32, i32]
     lib.wf_supported.restype = i32
+    lib.wf_tile_count.argtypes = []
+    lib.wf_tile_count.restype = i32
+    lib.wf_ctx_set_tile.argtypes = [vp, i32]
+    lib.wf_ctx_set_tile.restype = i32
+    lib.wf_ctx_get_tile.argtypes = [vp]
+    lib.wf_ctx_get_tile.restype = i32
     lib.wf_strerror.argtypes = [i32]
     lib.wf_strerror.restype = ctypes.c_char_p
     _lib = lib
@@ -191,6 +198,20 @@ class Context:
 
     def set_profiling(self, on: bool):
         load().wf_ctx_set_profiling(self._h, 1 if on else 0)
+
+    @property
+    def tile(self) -> int:
+        return load().wf_ctx_get_tile(self._h)
+
+    def set_tile(self, tile: int) -> bool:
+        """Select a transit-buffer tiling; False if it is not built for this
+        context's size and precision."""
+        st = load().wf_ctx_set_tile(self._h, int(tile))
+        if st == -6:
+            return False
+        if st != 0:
+            raise WFError(st, "wf_ctx_set_tile")
+        return True
 
     def _check(self, t, shape, name, dtype=None):
         import torch

@@ -222,19 +222,53 @@ __global__ __launch_bounds__(256) void prep_spectra_kernel(const T* __restrict__
 }
 
 // ---------------------------------------------------------------------------
+// transit-buffer tiling
+// ---------------------------------------------------------------------------
+// B holds nx/2 complex columns per row: column 0 packs the two real-valued
+// columns k_x = 0 (re) and k_x = nx/2 (im) of the row spectrum, so the
+// column pass works on exactly nx/2 complex columns.  Layout:
+// [y / TR][kx / TC][TR][TC].  A row workgroup takes RW consecutive rows
+// (RW divides TR), a column workgroup one tile column of TC columns.
+
+// map a block index to a work index so that the `per` work items whose data
+// share HBM lines run on the same XCD (blocks go round-robin to the 8 XCDs)
+__device__ __forceinline__ int xcd_remap(int b, int n, int per) {
+  if (per <= 1 || (n % (8 * per)) != 0) return b;
+  const int x = b & 7, s = b >> 3;
+  return (s / per) * (8 * per) + x * per + (s % per);
+}
+
+template <class T>
+constexpr int lines_share(int elems) {
+  const int bytes = elems * 2 * (int)sizeof(T);
+  return bytes >= 128 ? 1 : 128 / bytes;
+}
+
+// copy `n` complex values in 16-byte units (n and both offsets even for float)
+template <class T>
+__device__ __forceinline__ void copy16(cx<T>* dst, const cx<T>* src) {
+  *reinterpret_cast<uint4*>(dst) = *reinterpret_cast<const uint4*>(src);
+}
+
+// ---------------------------------------------------------------------------
 // row kernel: inverse row FFT -> white-level update -> forward row FFT
 // ---------------------------------------------------------------------------
-template <class T, int NX, int MODE>
-__global__ __launch_bounds__((kTR / 2) * (NX / kE)) void row_kernel(SweepArgs<T> a, int k_local,
-                                                                    const T* __restrict__ xin,
-                                                                    T* __restrict__ xout) {
+// at least 2 waves per SIMD so that two blocks share a CU and one
+// block's memory phase overlaps another's FFT
+constexpr int kMinWaves = 2;
+
+template <class T, int NX, int TR, int TC, int RW, int MODE>
+__global__ __launch_bounds__((RW / 2) * (NX / kE), kMinWaves) void row_kernel(SweepArgs<T> a, int k_local,
+                                                                   const T* __restrict__ xin,
+                                                                   T* __restrict__ xout) {
   constexpr int NT = NX / kE;
-  constexpr int RP = kTR / 2;
-  constexpr int KPc = KP<NX, kTC>::value;
-  constexpr int BAND = kTR * KPc;
+  constexpr int RP = RW / 2;
+  constexpr int KPC = NX / 2;                 // packed half width
+  constexpr int SUB = RW * KPC;               // complex values of this block's rows
   constexpr int XS = padded<NX>::value;
-  constexpr int LDSN = (BAND > RP * XS) ? BAND : RP * XS;
-  __shared__ cx<T> lds[LDSN];
+  constexpr int LDSN = (SUB > RP * XS) ? SUB : RP * XS;
+  constexpr int EPC = 16 / (2 * (int)sizeof(T));  // complex values per 16 bytes
+  __shared__ __align__(16) cx<T> lds[LDSN];
 
   T lt = (T)0;  // lambda * tau of the white level
   if constexpr (MODE == ROW_SWEEP) {
@@ -245,27 +279,37 @@ __global__ __launch_bounds__((kTR / 2) * (NX / kE)) void row_kernel(SweepArgs<T>
     lt = (T)(a.lam[kk] * a.tauW);
   }
   const int tid = threadIdx.x;
-  const int band = blockIdx.x;
-  cx<T>* gB = (cx<T>*)a.B + (size_t)band * BAND;
+  const int blk = xcd_remap(blockIdx.x, gridDim.x, min(TR / RW, lines_share<T>(RW * TC)));
+  const int y0 = blk * RW;
+  const int r0 = y0 % TR;
+  cx<T>* gband = (cx<T>*)a.B + (size_t)(y0 / TR) * (TR * KPC) + r0 * TC;
   const cx<T>* tw = (const cx<T>*)a.twx;
   const int p = tid / NT, t = tid - p * NT;
-  const int y0 = band * kTR + 2 * p;
+  const int ya = y0 + 2 * p;
   cx<T> reg[kE];
 
   if constexpr (MODE == ROW_SWEEP || MODE == ROW_C2R) {
-    for (int e = tid; e < BAND; e += blockDim.x) lds[e] = gB[e];
+    for (int e = tid * EPC; e < SUB; e += blockDim.x * EPC) {
+      const int g = e / (RW * TC), w = e - g * (RW * TC);
+      copy16(&lds[e], &gband[g * (TR * TC) + w]);
+    }
     __syncthreads();
-    // Z = A + i B for the row pair (2p, 2p+1); A, B Hermitian in k_x
+    // Z = A + i B for the row pair; A, B Hermitian in k_x; slot 0 packs
+    // (re of k_x = 0, re of k_x = nx/2)
 #pragma unroll
     for (int q = 0; q < kE; ++q) {
       const int k = t + NT * q;
       const bool hi = k > NX / 2;
       const int kx = hi ? NX - k : k;
-      const int li = (kx / kTC) * (kTR * kTC) + (2 * p) * kTC + (kx % kTC);
-      cx<T> A = lds[li], Bv = lds[li + kTC];
-      if (kx == 0 || kx == NX / 2) {
+      const int ks = (kx == NX / 2) ? 0 : kx;
+      const int li = (ks / TC) * (RW * TC) + (2 * p) * TC + (ks % TC);
+      cx<T> A = lds[li], Bv = lds[li + TC];
+      if (kx == 0) {
         A.im = (T)0;
         Bv.im = (T)0;
+      } else if (kx == NX / 2) {
+        A = cx<T>{A.im, (T)0};
+        Bv = cx<T>{Bv.im, (T)0};
       }
       if (hi) {
         A.im = -A.im;
@@ -279,25 +323,35 @@ __global__ __launch_bounds__((kTR / 2) * (NX / kE)) void row_kernel(SweepArgs<T>
     if constexpr (MODE == ROW_C2R) {
 #pragma unroll
       for (int q = 0; q < kE; ++q) {
-        const size_t i0 = (size_t)y0 * NX + t + NT * q;
+        const size_t i0 = (size_t)ya * NX + t + NT * q;
         xout[i0] = reg[q].re * sc;
         xout[i0 + NX] = reg[q].im * sc;
       }
       return;
     } else {
 #pragma unroll
-      for (int q = 0; q < kE; ++q) {
-        const size_t i0 = (size_t)y0 * NX + t + NT * q;
-        const size_t i1 = i0 + NX;
-        const T d1a = reg[q].re * sc, d1b = reg[q].im * sc;
-        reg[q] = cx<T>{white_update<T>(a.d[i0], a.nbar2[i0], d1a, lt),
-                       white_update<T>(a.d[i1], a.nbar2[i1], d1b, lt)};
+      for (int h = 0; h < kE; h += kE / 2) {
+        T dv0[kE / 2], dv1[kE / 2], nb0[kE / 2], nb1[kE / 2];
+#pragma unroll
+        for (int q = 0; q < kE / 2; ++q) {
+          const size_t i0 = (size_t)ya * NX + t + NT * (h + q);
+          dv0[q] = a.d[i0];
+          dv1[q] = a.d[i0 + NX];
+          nb0[q] = a.nbar2[i0];
+          nb1[q] = a.nbar2[i0 + NX];
+        }
+#pragma unroll
+        for (int q = 0; q < kE / 2; ++q) {
+          const T d1a = reg[h + q].re * sc, d1b = reg[h + q].im * sc;
+          reg[h + q] = cx<T>{white_update<T>(dv0[q], nb0[q], d1a, lt),
+                             white_update<T>(dv1[q], nb1[q], d1b, lt)};
+        }
       }
     }
   } else {  // ROW_R2C
 #pragma unroll
     for (int q = 0; q < kE; ++q) {
-      const size_t i0 = (size_t)y0 * NX + t + NT * q;
+      const size_t i0 = (size_t)ya * NX + t + NT * q;
       reg[q] = cx<T>{xin[i0], xin[i0 + NX]};
     }
   }
@@ -305,20 +359,27 @@ __global__ __launch_bounds__((kTR / 2) * (NX / kE)) void row_kernel(SweepArgs<T>
 #pragma unroll
   for (int q = 0; q < kE; ++q) lds[p * XS + lpad(t + NT * q)] = reg[q];
   __syncthreads();
-  // split Z into the two rows' spectra and store the band in tile order
-  for (int e = tid; e < BAND; e += blockDim.x) {
-    const int tile = e / (kTR * kTC);
-    const int w = e - tile * (kTR * kTC);
-    const int r = w / kTC, c = w - r * kTC;
-    const int kx = tile * kTC + c;
-    cx<T> v = {(T)0, (T)0};
-    if (kx <= NX / 2) {
-      const cx<T>* Z = lds + (r >> 1) * XS;
-      const cx<T> zk = Z[lpad(kx)], zm = Z[lpad((NX - kx) & (NX - 1))];
-      v = (r & 1) ? cx<T>{(zk.im + zm.im) * (T)0.5, (zm.re - zk.re) * (T)0.5}
-                  : cx<T>{(zk.re + zm.re) * (T)0.5, (zk.im - zm.im) * (T)0.5};
+  // split Z into the two rows' spectra; write this block's rows, tile order
+  for (int e = tid * EPC; e < SUB; e += blockDim.x * EPC) {
+    cx<T> v[EPC];
+#pragma unroll
+    for (int u = 0; u < EPC; ++u) {
+      const int eu = e + u;
+      const int g = eu / (RW * TC), w = eu - g * (RW * TC);
+      const int rr = w / TC, c = w - rr * TC;
+      const int kx = g * TC + c;
+      const cx<T>* Z = lds + (rr >> 1) * XS;
+      if (kx == 0) {
+        const cx<T> z0 = Z[0], zn = Z[lpad(NX / 2)];
+        v[u] = (rr & 1) ? cx<T>{z0.im, zn.im} : cx<T>{z0.re, zn.re};
+      } else {
+        const cx<T> zk = Z[lpad(kx)], zm = Z[lpad(NX - kx)];
+        v[u] = (rr & 1) ? cx<T>{(zk.im + zm.im) * (T)0.5, (zm.re - zk.re) * (T)0.5}
+                        : cx<T>{(zk.re + zm.re) * (T)0.5, (zk.im - zm.im) * (T)0.5};
+      }
     }
-    gB[e] = v;
+    const int g = e / (RW * TC), w = e - g * (RW * TC);
+    copy16(&gband[g * (TR * TC) + w], v);
   }
 }
 
@@ -330,14 +391,60 @@ __device__ __forceinline__ cx<T> wavg(T wa, cx<T> a, T wb, cx<T> b, T inv) {
   return cx<T>{(wa * a.re + wb * b.re) * inv, (wa * a.im + wb * b.im) * inv};
 }
 
-template <class T, int NY, int MODE>
-__global__ __launch_bounds__(kTC * (NY / kE)) void col_kernel(SweepArgs<T> a, int k_local,
-                                                              cx<T>* __restrict__ spec,
-                                                              double lam_init) {
+// Per-mode coefficients of the chain at one sweep.
+template <class T>
+struct ChainCoef {
+  T TW, TA, TB, SA, cB, nxr;
+  int fk;
+  bool store_first;
+};
+
+// One mode: t_2 (white messenger, Fourier) in, field for the white level out.
+// Reads and writes the stored Fourier-side fields of this mode.
+template <class T, int FK>
+__device__ __forceinline__ cx<T> chain_mode(const SweepArgs<T>& a, const ChainCoef<T>& k, int kx,
+                                            int ky, size_t idx, cx<T> t2, T s, T nbA, T pst,
+                                            cx<T> tAo, cx<T> dAo, cx<T> tBo) {
+  cx<T>* tA = (cx<T>*)a.tA;
+  if constexpr (FK == FK_NONE) {
+    if (k.store_first) tA[idx] = t2;
+    return cscale(t2, s / (s + k.TW));
+  } else if constexpr (FK == FK_ARRAY_STRIPE) {
+    const T nbB = (kx == 0 ? k.nxr * pst : (T)0) + k.cB;
+    const cx<T> dBn = wavg(nbB, t2, k.TW, tBo, (T)1 / (nbB + k.TW));
+    const cx<T> tBn = wavg(k.TB, dBn, nbB, dAo, (T)1 / (nbB + k.TB));
+    const cx<T> dAn = wavg(nbA, tBn, k.TB, tAo, (T)1 / (nbA + k.TB));
+    const cx<T> so = cscale(tAo, s / (s + k.SA));
+    const cx<T> tAn = wavg(k.TA, dAn, nbA, so, (T)1 / (nbA + k.TA));
+    ((cx<T>*)a.tB)[idx] = tBn;
+    ((cx<T>*)a.dA)[idx] = dAn;
+    tA[idx] = tAn;
+    return dBn;
+  } else {
+    // one Fourier level: an array level or the stripe level
+    T nb;
+    if constexpr (FK == FK_ARRAY) nb = nbA;
+    else nb = (kx == 0 ? k.nxr * pst : (T)0) + k.cB;
+    const cx<T> dAn = wavg(nb, t2, k.TW, tAo, (T)1 / (nb + k.TW));
+    const cx<T> so = cscale(tAo, s / (s + k.SA));
+    const cx<T> tAn = wavg(k.TA, dAn, nb, so, (T)1 / (nb + k.TA));
+    tA[idx] = tAn;
+    return dAn;
+  }
+}
+
+template <class T>
+__device__ __forceinline__ cx<T> cconj(cx<T> v) { return cx<T>{v.re, -v.im}; }
+
+template <class T, int NY, int TR, int TC, int MODE, int FK>
+__global__ __launch_bounds__(TC * (NY / kE), kMinWaves) void col_kernel(SweepArgs<T> a, int k_local,
+                                                             cx<T>* __restrict__ spec,
+                                                             double lam_init) {
   constexpr int NT = NY / kE;
   constexpr int YS = padded<NY>::value;
-  constexpr int TRTC = kTR * kTC;
-  __shared__ cx<T> lds[kTC * YS];
+  constexpr int TRTC = TR * TC;
+  constexpr int EPC = 16 / (2 * (int)sizeof(T));
+  __shared__ __align__(16) cx<T> lds[TC * YS];
 
   double lam = 0.0, lamp = 0.0;
   bool store_first = false;
@@ -353,12 +460,13 @@ __global__ __launch_bounds__(kTC * (NY / kE)) void col_kernel(SweepArgs<T> a, in
     store_first = (kk == klast);
   }
   const int tid = threadIdx.x;
-  const int g = blockIdx.x;
-  const int G = a.kp / kTC;
+  const int G = a.nx / 2 / TC;
+  const int g = xcd_remap(blockIdx.x, G, lines_share<T>(TRTC));
   const int c = tid / NT, t = tid - c * NT;
-  const int kx = g * kTC + c;
+  const int kxc = g * TC + c;          // column of B (0 packs k_x = 0 and nx/2)
+  const bool packed = (kxc == 0);
   const int nh = a.nx / 2 + 1;
-  const bool valid = kx < nh;
+  const int kxn = a.nx / 2;
   cx<T>* gB = (cx<T>*)a.B;
   const cx<T>* tw = (const cx<T>*)a.twy;
   cx<T> reg[kE];
@@ -367,13 +475,27 @@ __global__ __launch_bounds__(kTC * (NY / kE)) void col_kernel(SweepArgs<T> a, in
 #pragma unroll
     for (int q = 0; q < kE; ++q) {
       const int ky = t + NT * q;
-      reg[q] = valid ? spec[(size_t)ky * nh + kx] : cx<T>{(T)0, (T)0};
+      if (packed) {
+        // Hermitian parts of the k_x = 0 and nx/2 columns (irfft2 semantics)
+        const int km = (NY - ky) & (NY - 1);
+        const cx<T> a0 = spec[(size_t)ky * nh], b0 = spec[(size_t)km * nh];
+        const cx<T> an = spec[(size_t)ky * nh + kxn], bn = spec[(size_t)km * nh + kxn];
+        const cx<T> h0 = cscale(a0 + cconj(b0), (T)0.5), hn = cscale(an + cconj(bn), (T)0.5);
+        reg[q] = cx<T>{h0.re - hn.im, h0.im + hn.re};
+      } else {
+        reg[q] = spec[(size_t)ky * nh + kxc];
+      }
     }
   } else {
-    for (int e = tid; e < kTC * NY; e += blockDim.x) {
+    for (int e = tid * EPC; e < TC * NY; e += blockDim.x * EPC) {
       const int yb = e / TRTC, w = e - yb * TRTC;
-      const int r = w / kTC, cc = w - r * kTC;
-      lds[cc * YS + lpad(yb * kTR + r)] = gB[((size_t)yb * G + g) * TRTC + w];
+      cx<T> v[EPC];
+      copy16(v, &gB[((size_t)yb * G + g) * TRTC + w]);
+#pragma unroll
+      for (int u = 0; u < EPC; ++u) {
+        const int r = (w + u) / TC, cc = (w + u) - r * TC;
+        lds[cc * YS + lpad(yb * TR + r)] = v[u];
+      }
     }
     __syncthreads();
 #pragma unroll
@@ -382,60 +504,103 @@ __global__ __launch_bounds__(kTC * (NY / kE)) void col_kernel(SweepArgs<T> a, in
     fft<T, NY, false>(reg, lds + c * YS, t, tw);
   }
 
-  if constexpr (MODE == COL_FWD_OUT) {
-    if (valid) {
+  // packed column (block 0, column 0): split Z = C0 + i CN into the k_x = 0
+  // and k_x = nx/2 spectra; C0 stays in registers, CN goes to this column's
+  // LDS slots (only this column's threads touch them until the inverse FFT)
+  cx<T>* cnl = lds;  // column 0's region
+  if constexpr (MODE != COL_INV_IN) {
+    if (g == 0) {
+      if (packed) {
 #pragma unroll
-      for (int q = 0; q < kE; ++q) spec[(size_t)(t + NT * q) * nh + kx] = reg[q];
+        for (int q = 0; q < kE; ++q) lds[lpad(t + NT * q)] = reg[q];
+      }
+      __syncthreads();
+      cx<T> cnv[kE];
+      if (packed) {
+#pragma unroll
+        for (int q = 0; q < kE; ++q) {
+          const int ky = t + NT * q;
+          const cx<T> zk = reg[q], zm = lds[lpad((NY - ky) & (NY - 1))];
+          reg[q] = cx<T>{(zk.re + zm.re) * (T)0.5, (zk.im - zm.im) * (T)0.5};
+          cnv[q] = cx<T>{(zk.im + zm.im) * (T)0.5, (zm.re - zk.re) * (T)0.5};
+        }
+      }
+      __syncthreads();
+      if (packed) {
+#pragma unroll
+        for (int q = 0; q < kE; ++q) cnl[lpad(t + NT * q)] = cnv[q];
+      }
+    }
+  }
+
+  if constexpr (MODE == COL_FWD_OUT) {
+#pragma unroll
+    for (int q = 0; q < kE; ++q) {
+      const size_t row = (size_t)(t + NT * q) * nh;
+      spec[row + kxc] = reg[q];
+      if (packed) spec[row + kxn] = cnl[lpad(t + NT * q)];
     }
     return;
   }
 
   if constexpr (MODE == COL_SWEEP) {
-    const T TW = (T)(lam * a.tauW), TA = (T)(lam * a.tauA), TB = (T)(lam * a.tauB);
-    const T SA = (T)(lamp * a.tauA);
-    cx<T>* tA = (cx<T>*)a.tA;
-    cx<T>* dA = (cx<T>*)a.dA;
-    cx<T>* tB = (cx<T>*)a.tB;
-    const T cB = (T)a.cB;
-    const T nxr = (T)a.nx;
-    if (valid) {
-#pragma unroll
+    ChainCoef<T> k;
+    k.TW = (T)(lam * a.tauW);
+    k.TA = (T)(lam * a.tauA);
+    k.TB = (T)(lam * a.tauB);
+    k.SA = (T)(lamp * a.tauA);
+    k.cB = (T)a.cB;
+    k.nxr = (T)a.nx;
+    k.fk = a.fk;
+    k.store_first = store_first;
+    constexpr bool hasA = FK != FK_NONE;
+    constexpr bool hasB = FK == FK_ARRAY_STRIPE;
+    constexpr bool needNb = FK == FK_ARRAY || FK == FK_ARRAY_STRIPE;
+    constexpr bool needP = FK == FK_STRIPE || FK == FK_ARRAY_STRIPE;
+    const cx<T> z = {(T)0, (T)0};
+    // the k_x = nx/2 half of the packed column (its own state)
+    if (packed) {
       for (int q = 0; q < kE; ++q) {
         const int ky = t + NT * q;
-        const size_t idx = (size_t)kx * NY + ky;
-        const cx<T> t2 = reg[q];
-        const T s = a.sc[idx];
-        cx<T> out;
-        if (a.fk == FK_NONE) {
-          out = cscale(t2, s / (s + TW));
-          if (store_first) tA[idx] = t2;
-        } else if (a.fk == FK_ARRAY_STRIPE) {
-          const T nbB = (kx == 0 ? nxr * a.pst[ky] : (T)0) + cB;
-          const T nbA = a.nbA[idx];
-          const cx<T> tBo = tB[idx], dAo = dA[idx], tAo = tA[idx];
-          const cx<T> dBn = wavg(nbB, t2, TW, tBo, (T)1 / (nbB + TW));
-          const cx<T> tBn = wavg(TB, dBn, nbB, dAo, (T)1 / (nbB + TB));
-          const cx<T> dAn = wavg(nbA, tBn, TB, tAo, (T)1 / (nbA + TB));
-          const cx<T> so = cscale(tAo, s / (s + SA));
-          const cx<T> tAn = wavg(TA, dAn, nbA, so, (T)1 / (nbA + TA));
-          tB[idx] = tBn;
-          dA[idx] = dAn;
-          tA[idx] = tAn;
-          out = dBn;
-        } else {  // one Fourier level: an array level or the stripe level
-          const T nbA = (a.fk == FK_ARRAY) ? a.nbA[idx] : (kx == 0 ? nxr * a.pst[ky] : (T)0) + cB;
-          const cx<T> tAo = tA[idx];
-          const cx<T> dAn = wavg(nbA, t2, TW, tAo, (T)1 / (nbA + TW));
-          const cx<T> so = cscale(tAo, s / (s + SA));
-          const cx<T> tAn = wavg(TA, dAn, nbA, so, (T)1 / (nbA + TA));
-          tA[idx] = tAn;
-          out = dAn;
-        }
-        reg[q] = out;
+        const size_t idx = (size_t)kxn * NY + ky;
+        const int li = lpad(ky);
+        cnl[li] = chain_mode<T, FK>(a, k, kxn, ky, idx, cnl[li], a.sc[idx],
+                             needNb ? a.nbA[idx] : (T)0, needP ? a.pst[ky] : (T)0,
+                             hasA ? ((cx<T>*)a.tA)[idx] : z, hasB ? ((cx<T>*)a.dA)[idx] : z,
+                             hasB ? ((cx<T>*)a.tB)[idx] : z);
       }
-    } else {
+    }
+    // this column: loads batched by quarters, then the updates
+    constexpr int QB = kE / 4;
 #pragma unroll
-      for (int q = 0; q < kE; ++q) reg[q] = cx<T>{(T)0, (T)0};
+    for (int h = 0; h < kE; h += QB) {
+      T sv[QB], nv[QB], pv[QB];
+      cx<T> ta[QB], da[QB], tb[QB];
+#pragma unroll
+      for (int q = 0; q < QB; ++q) {
+        const int ky = t + NT * (h + q);
+        const size_t idx = (size_t)kxc * NY + ky;
+        sv[q] = a.sc[idx];
+        nv[q] = needNb ? a.nbA[idx] : (T)0;
+        pv[q] = needP ? a.pst[ky] : (T)0;
+        ta[q] = hasA ? ((const cx<T>*)a.tA)[idx] : z;
+        da[q] = hasB ? ((const cx<T>*)a.dA)[idx] : z;
+        tb[q] = hasB ? ((const cx<T>*)a.tB)[idx] : z;
+      }
+#pragma unroll
+      for (int q = 0; q < QB; ++q) {
+        const int ky = t + NT * (h + q);
+        const size_t idx = (size_t)kxc * NY + ky;
+        reg[h + q] = chain_mode<T, FK>(a, k, kxc, ky, idx, reg[h + q], sv[q], nv[q], pv[q],
+                                       ta[q], da[q], tb[q]);
+      }
+    }
+    if (packed) {
+#pragma unroll
+      for (int q = 0; q < kE; ++q) {
+        const cx<T> cv = cnl[lpad(t + NT * q)];
+        reg[q] = cx<T>{reg[q].re - cv.im, reg[q].im + cv.re};
+      }
     }
   }
 
@@ -450,9 +615,13 @@ __global__ __launch_bounds__(kTC * (NY / kE)) void col_kernel(SweepArgs<T> a, in
 #pragma unroll
     for (int q = 0; q < kE; ++q) {
       const int ky = t + NT * q;
-      const size_t idx = (size_t)kx * NY + ky;
-      cx<T> v = reg[q];
-      if (valid) {
+      cx<T> out[2];
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        if (h == 1 && !packed) break;
+        const int kx = h == 0 ? kxc : kxn;
+        const size_t idx = (size_t)kx * NY + ky;
+        cx<T> v = h == 0 ? reg[q] : cnl[lpad(ky)];
         if (a.fk == FK_NONE) {
           const T s = a.sc[idx];
           v = cscale(v, s / (s + TW0));
@@ -463,21 +632,27 @@ __global__ __launch_bounds__(kTC * (NY / kE)) void col_kernel(SweepArgs<T> a, in
             tB[idx] = v;
           }
         }
-      } else {
-        v = cx<T>{(T)0, (T)0};
+        out[h] = v;
       }
-      reg[q] = v;
+      reg[q] = packed ? cx<T>{out[0].re - out[1].im, out[0].im + out[1].re} : out[0];
     }
   }
 
+  // the inverse transform reuses column 0's LDS region
+  __syncthreads();
   fft<T, NY, true>(reg, lds + c * YS, t, tw);
 #pragma unroll
   for (int q = 0; q < kE; ++q) lds[c * YS + lpad(t + NT * q)] = reg[q];
   __syncthreads();
-  for (int e = tid; e < kTC * NY; e += blockDim.x) {
+  for (int e = tid * EPC; e < TC * NY; e += blockDim.x * EPC) {
     const int yb = e / TRTC, w = e - yb * TRTC;
-    const int r = w / kTC, cc = w - r * kTC;
-    gB[((size_t)yb * G + g) * TRTC + w] = lds[cc * YS + lpad(yb * kTR + r)];
+    cx<T> v[EPC];
+#pragma unroll
+    for (int u = 0; u < EPC; ++u) {
+      const int r = (w + u) / TC, cc = (w + u) - r * TC;
+      v[u] = lds[cc * YS + lpad(yb * TR + r)];
+    }
+    copy16(&gB[((size_t)yb * G + g) * TRTC + w], v);
   }
 }
 

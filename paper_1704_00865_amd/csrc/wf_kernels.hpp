@@ -7,9 +7,6 @@
 
 namespace wf {
 
-// transit-buffer tile of the sweep (rows x half-spectrum columns per tile)
-constexpr int kTR = 8;
-constexpr int kTC = 4;
 // tile of the float64 monitor transit buffers
 constexpr int kTRM = 2;
 constexpr int kTCM = 2;
@@ -51,7 +48,7 @@ struct DevSched {
 
 template <class T>
 struct SweepArgs {
-  void* B;                // transit buffer, cx<T>, tiled [y/TR][kx/TC][TR][TC]
+  void* B;                // transit buffer, cx<T>, nx/2 packed columns, tiled [y/TR][kx/TC][TR][TC]
   void* tA;               // state: t of the signal-side Fourier level (or t_white copy)
   void* dA;               // state: d of that level (FK_ARRAY_STRIPE only)
   void* tB;               // state: t of the stripe level (FK_ARRAY_STRIPE only)
@@ -64,7 +61,7 @@ struct SweepArgs {
   const void* twy;        // w_ny^j table, cx<T>
   const DevSched* sch;
   const double* lam;      // lambda per sweep index
-  int32_t nx, ny, kp;     // kp: padded half width (multiple of kTC)
+  int32_t nx, ny;
   int32_t fk;             // FourierKind
   double tauA, tauB, tauW;  // messenger variances (A: signal-side level)
   double cB;              // Nbar offset of a stripe level (phi - tau)

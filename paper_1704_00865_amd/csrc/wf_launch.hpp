@@ -7,12 +7,20 @@
 
 namespace wf {
 
+// transit-buffer tile: TR rows x TC columns per tile, RW rows per row block
+struct TileCfg {
+  int TR, TC, RW;
+};
+constexpr int kNumTiles = 7;
+constexpr int kTileDefault = 1;
+extern const TileCfg kTiles[kNumTiles];
+
 template <class T>
-hipError_t launch_row(int mode, const SweepArgs<T>& a, int k_local, const T* xin, T* xout,
+hipError_t launch_row(int cfg, int mode, const SweepArgs<T>& a, int k_local, const T* xin, T* xout,
                       hipStream_t st);
 template <class T>
-hipError_t launch_col(int mode, const SweepArgs<T>& a, int k_local, void* spec, double lam_init,
-                      hipStream_t st);
+hipError_t launch_col(int cfg, int mode, const SweepArgs<T>& a, int k_local, void* spec,
+                      double lam_init, hipStream_t st);
 template <class T>
 hipError_t launch_mon_col(const MonArgs<T>& m, int mode, double lam_out, hipStream_t st);
 template <class T>

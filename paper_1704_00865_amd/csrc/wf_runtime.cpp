@@ -31,7 +31,8 @@ constexpr int kProfSlots = 512;
 
 struct Ctx {
   int ny = 0, nx = 0, prec = 0;
-  int nh = 0, kp = 0, kpm = 0;
+  int nh = 0, kpm = 0;
+  int tile = kTileDefault;
   size_t esz = 0;
   int device = 0;
   void* B = nullptr;
@@ -124,7 +125,6 @@ wf_status create(const wf_shape* sh, Ctx** out) {
   c->prec = sh->precision;
   c->esz = c->prec == WF_F64 ? 8 : 4;
   c->nh = c->nx / 2 + 1;
-  c->kp = ((c->nh + kTC - 1) / kTC) * kTC;
   c->kpm = ((c->nh + kTCM - 1) / kTCM) * kTCM;
   (void)hipGetDevice(&c->device);
   const size_t ny = c->ny, nx = c->nx, nh = c->nh, esz = c->esz;
@@ -135,7 +135,7 @@ wf_status create(const wf_shape* sh, Ctx** out) {
     free_ctx(c);                                      \
     return st;                                        \
   }
-  A(c->B, ny * c->kp * 2 * esz);
+  A(c->B, ny * (nx / 2) * 2 * esz);
   A(c->tA, modes * 2 * esz);
   A(c->dA, modes * 2 * esz);
   A(c->tB, modes * 2 * esz);
@@ -280,7 +280,6 @@ SweepArgs<T> sweep_args(Ctx* c, const wf_inputs* in, const Chain& ch) {
   a.lam = c->lam;
   a.nx = c->nx;
   a.ny = c->ny;
-  a.kp = c->kp;
   a.fk = ch.fk;
   a.tauA = ch.tauA;
   a.tauB = ch.tauB;
@@ -410,10 +409,10 @@ wf_status solve_t(Ctx* c, const wf_inputs* in, const wf_schedule* s, const void*
   // 4. initial state
   const size_t modes_b = (size_t)c->nh * c->ny * 2 * c->esz;
   if (s_init) {
-    WF_TRY(launch_row<T>(ROW_R2C, a, 0, (const T*)s_init, nullptr, st));
-    WF_TRY(launch_col<T>(COL_INIT, a, 0, nullptr, lam[0], st));
+    WF_TRY(launch_row<T>(c->tile, ROW_R2C, a, 0, (const T*)s_init, nullptr, st));
+    WF_TRY(launch_col<T>(c->tile, COL_INIT, a, 0, nullptr, lam[0], st));
   } else {
-    WF_TRY(hipMemsetAsync(c->B, 0, (size_t)c->ny * c->kp * 2 * c->esz, st));
+    WF_TRY(hipMemsetAsync(c->B, 0, (size_t)c->ny * (c->nx / 2) * 2 * c->esz, st));
     WF_TRY(hipMemsetAsync(c->tA, 0, modes_b, st));
     WF_TRY(hipMemsetAsync(c->dA, 0, modes_b, st));
     WF_TRY(hipMemsetAsync(c->tB, 0, modes_b, st));
@@ -435,9 +434,9 @@ wf_status solve_t(Ctx* c, const wf_inputs* in, const wf_schedule* s, const void*
     hipEvent_t* ev = sample ? &c->prof_ev[5 * ci] : nullptr;
     for (int k = 0; k < K; ++k) {
       if (sample && k == 0) WF_TRY(hipEventRecord(ev[0], st));
-      WF_TRY(launch_row<T>(ROW_SWEEP, a, k, nullptr, nullptr, st));
+      WF_TRY(launch_row<T>(c->tile, ROW_SWEEP, a, k, nullptr, nullptr, st));
       if (sample && k == 0) WF_TRY(hipEventRecord(ev[1], st));
-      WF_TRY(launch_col<T>(COL_SWEEP, a, k, nullptr, 0.0, st));
+      WF_TRY(launch_col<T>(c->tile, COL_SWEEP, a, k, nullptr, 0.0, st));
       if (sample && k == 0) WF_TRY(hipEventRecord(ev[2], st));
     }
     if (sample) WF_TRY(hipEventRecord(ev[3], st));
@@ -506,11 +505,11 @@ wf_status fft_t(Ctx* c, const void* src, void* dst, bool forward, hipStream_t st
   Chain ch;
   SweepArgs<T> a = sweep_args<T>(c, nullptr, ch);
   if (forward) {
-    WF_TRY(launch_row<T>(ROW_R2C, a, 0, (const T*)src, nullptr, st));
-    WF_TRY(launch_col<T>(COL_FWD_OUT, a, 0, dst, 0.0, st));
+    WF_TRY(launch_row<T>(kTileDefault, ROW_R2C, a, 0, (const T*)src, nullptr, st));
+    WF_TRY(launch_col<T>(kTileDefault, COL_FWD_OUT, a, 0, dst, 0.0, st));
   } else {
-    WF_TRY(launch_col<T>(COL_INV_IN, a, 0, const_cast<void*>(src), 0.0, st));
-    WF_TRY(launch_row<T>(ROW_C2R, a, 0, nullptr, (T*)dst, st));
+    WF_TRY(launch_col<T>(kTileDefault, COL_INV_IN, a, 0, const_cast<void*>(src), 0.0, st));
+    WF_TRY(launch_row<T>(kTileDefault, ROW_C2R, a, 0, nullptr, (T*)dst, st));
   }
   WF_TRY(hipStreamSynchronize(st));
   return WF_OK;
@@ -588,6 +587,26 @@ wf_status wf_ctx_set_profiling(void* ctx, int32_t enable) {
 }
 
 int32_t wf_supported(int32_t ny, int32_t nx, int32_t precision) { return supported(ny, nx, precision); }
+
+int32_t wf_tile_count(void) { return kNumTiles; }
+
+wf_status wf_ctx_set_tile(void* ctx, int32_t tile) {
+  Ctx* c = (Ctx*)ctx;
+  if (!c || tile < 0 || tile >= kNumTiles) return WF_EINVAL;
+  // the default tiling is built for every size; the others for float32
+  // 2048 x 2048 maps only
+  const bool built = tile == kTileDefault || (c->prec == WF_F32 && c->nx == 2048 && c->ny == 2048);
+  if (!built) return WF_EUNSUPPORTED;
+  const TileCfg& t = kTiles[tile];
+  if (c->ny % t.TR != 0 || (c->nx / 2) % t.TC != 0) return WF_EUNSUPPORTED;
+  c->tile = tile;
+  return WF_OK;
+}
+
+int32_t wf_ctx_get_tile(void* ctx) {
+  Ctx* c = (Ctx*)ctx;
+  return c ? c->tile : -1;
+}
 
 const char* wf_strerror(int32_t s) {
   switch (s) {

@@ -243,3 +243,28 @@ def test_bitwise_deterministic(gpu_lib):
     b, rb, tb = ctx.solve(*_tensors(p, "f32"), schedule=sched)
     np.testing.assert_array_equal(a, b.cpu().numpy())
     np.testing.assert_array_equal(ta, tb)
+
+
+def test_tilings_give_identical_results(gpu_lib):
+    """Every transit-buffer tiling only moves data differently, so all of
+    them must give bit-identical sweeps (2048x2048, float32)."""
+    p = synth.named_config("c3")
+    ctx = gpu_lib.Context(2048, 2048, "f32")
+    args = _tensors(p, "f32")
+    sched = gpu_lib.Schedule(lambdas=[1e4, 3e3, 1e3, 300.0, 100.0, 30.0], rtol=0.0,
+                             max_sweeps=6, monitor_every=3)
+    ref = None
+    n_built = 0
+    for tile in range(gpu_lib.load().wf_tile_count()):
+        if not ctx.set_tile(tile):
+            continue
+        n_built += 1
+        print(f"tiling {tile}", flush=True)
+        s, rep, trace = ctx.solve(*args, schedule=sched)
+        s = s.cpu().numpy().copy()
+        if ref is None:
+            ref = (s, trace)
+        else:
+            np.testing.assert_array_equal(s, ref[0])
+            np.testing.assert_array_equal(trace, ref[1])
+    assert n_built >= 2
