@@ -21,7 +21,8 @@ __all__ = [
     "WFError", "STATUS", "CHAINS",
 ]
 
-_LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libwf.so")
+_LIB_PATH = os.environ.get("WF_LIBRARY") or os.path.join(
+    os.path.dirname(os.path.abspath(__file__)), "libwf.so")
 _lib = None
 
 STATUS = {0: "OK", 1: "NOT_CONVERGED", -1: "EINVAL", -2: "ENOTPD", -3: "ENONFINITE",

@@ -37,17 +37,20 @@ def _hipcc() -> str:
     raise RuntimeError("hipcc not found")
 
 
-def build(verbose: bool = False, jobs: int = 2) -> str:
+def build(verbose: bool = False, jobs: int = 2, defines=(), out: str = LIB,
+          build_dir: str = BUILD_DIR) -> str:
     """Compile every source for gfx950 and link the shared library.  Always
-    recompiles (objects go to a temporary folder that is removed after)."""
+    recompiles (objects go to a temporary folder that is removed after).
+    ``defines`` are extra -D options; ``out`` the library path."""
     hipcc = _hipcc()
-    os.makedirs(BUILD_DIR, exist_ok=True)
+    os.makedirs(build_dir, exist_ok=True)
     objs = []
     procs = []
     for src in SOURCES:
-        obj = os.path.join(BUILD_DIR, os.path.splitext(src)[0] + ".o")
+        obj = os.path.join(build_dir, os.path.splitext(src)[0] + ".o")
         objs.append(obj)
-        cmd = [hipcc, "-x", "hip", *HIPCC_FLAGS, "-I", INCLUDE, "-I", CSRC, "-c",
+        cmd = [hipcc, "-x", "hip", *HIPCC_FLAGS, *[f"-D{d}" for d in defines],
+               "-I", INCLUDE, "-I", CSRC, "-c",
                os.path.join(CSRC, src), "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
@@ -57,14 +60,14 @@ def build(verbose: bool = False, jobs: int = 2) -> str:
             _wait(procs.pop(0))
     while procs:
         _wait(procs.pop(0))
-    tmp = LIB + ".tmp"
+    tmp = out + ".tmp"
     cmd = [hipcc, "--offload-arch=gfx950", "-shared", "-fPIC", *objs, "-o", tmp]
     if verbose:
         print(" ".join(cmd), flush=True)
     _wait((cmd, subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True)))
-    os.replace(tmp, LIB)
-    shutil.rmtree(BUILD_DIR, ignore_errors=True)
-    return LIB
+    os.replace(tmp, out)
+    shutil.rmtree(build_dir, ignore_errors=True)
+    return out
 
 
 def _wait(item):

@@ -253,6 +253,13 @@ __device__ __forceinline__ void copy16(cx<T>* dst, const cx<T>* src) {
 // ---------------------------------------------------------------------------
 // row kernel: inverse row FFT -> white-level update -> forward row FFT
 // ---------------------------------------------------------------------------
+// twiddle table staged in LDS when it is small (float32 up to 2048 points);
+// larger tables are read through the L1/L2 caches
+template <class T, int N>
+constexpr bool lds_twiddles() {
+  return N * 2 * (int)sizeof(T) <= 16384;
+}
+
 // at least 2 waves per SIMD so that two blocks share a CU and one
 // block's memory phase overlaps another's FFT
 constexpr int kMinWaves = 2;
@@ -269,6 +276,8 @@ __global__ __launch_bounds__((RW / 2) * (NX / kE), kMinWaves) void row_kernel(Sw
   constexpr int LDSN = (SUB > RP * XS) ? SUB : RP * XS;
   constexpr int EPC = 16 / (2 * (int)sizeof(T));  // complex values per 16 bytes
   __shared__ __align__(16) cx<T> lds[LDSN];
+  constexpr bool LTW = lds_twiddles<T, NX>();
+  __shared__ cx<T> twl[LTW ? NX : 1];
 
   T lt = (T)0;  // lambda * tau of the white level
   if constexpr (MODE == ROW_SWEEP) {
@@ -283,10 +292,14 @@ __global__ __launch_bounds__((RW / 2) * (NX / kE), kMinWaves) void row_kernel(Sw
   const int y0 = blk * RW;
   const int r0 = y0 % TR;
   cx<T>* gband = (cx<T>*)a.B + (size_t)(y0 / TR) * (TR * KPC) + r0 * TC;
-  const cx<T>* tw = (const cx<T>*)a.twx;
+  const cx<T>* twg = (const cx<T>*)a.twx;
   const int p = tid / NT, t = tid - p * NT;
   const int ya = y0 + 2 * p;
   cx<T> reg[kE];
+  if constexpr (LTW) {
+    for (int j = tid; j < NX; j += blockDim.x) twl[j] = twg[j];
+  }
+  const cx<T>* tw = LTW ? (const cx<T>*)twl : twg;
 
   if constexpr (MODE == ROW_SWEEP || MODE == ROW_C2R) {
     for (int e = tid * EPC; e < SUB; e += blockDim.x * EPC) {
@@ -329,6 +342,7 @@ __global__ __launch_bounds__((RW / 2) * (NX / kE), kMinWaves) void row_kernel(Sw
       }
       return;
     } else {
+      // white-level update, data and coefficients loaded in two batches
 #pragma unroll
       for (int h = 0; h < kE; h += kE / 2) {
         T dv0[kE / 2], dv1[kE / 2], nb0[kE / 2], nb1[kE / 2];
@@ -354,6 +368,7 @@ __global__ __launch_bounds__((RW / 2) * (NX / kE), kMinWaves) void row_kernel(Sw
       const size_t i0 = (size_t)ya * NX + t + NT * q;
       reg[q] = cx<T>{xin[i0], xin[i0 + NX]};
     }
+    if constexpr (LTW) __syncthreads();
   }
   fft<T, NX, false>(reg, lds + p * XS, t, tw);
 #pragma unroll
@@ -445,6 +460,8 @@ __global__ __launch_bounds__(TC * (NY / kE), kMinWaves) void col_kernel(SweepArg
   constexpr int TRTC = TR * TC;
   constexpr int EPC = 16 / (2 * (int)sizeof(T));
   __shared__ __align__(16) cx<T> lds[TC * YS];
+  constexpr bool LTW = lds_twiddles<T, NY>();
+  __shared__ cx<T> twl[LTW ? NY : 1];
 
   double lam = 0.0, lamp = 0.0;
   bool store_first = false;
@@ -468,8 +485,35 @@ __global__ __launch_bounds__(TC * (NY / kE), kMinWaves) void col_kernel(SweepArg
   const int nh = a.nx / 2 + 1;
   const int kxn = a.nx / 2;
   cx<T>* gB = (cx<T>*)a.B;
-  const cx<T>* tw = (const cx<T>*)a.twy;
+  const cx<T>* twg = (const cx<T>*)a.twy;
   cx<T> reg[kE];
+  if constexpr (LTW) {
+    for (int j = tid; j < NY; j += blockDim.x) twl[j] = twg[j];
+  }
+  const cx<T>* tw = LTW ? (const cx<T>*)twl : twg;
+
+  // per-mode state and coefficients of this column, loaded in two batches
+  constexpr int HB = kE / 2;
+  constexpr bool hasA = FK != FK_NONE;
+  constexpr bool hasB = FK == FK_ARRAY_STRIPE;
+  constexpr bool needNb = FK == FK_ARRAY || FK == FK_ARRAY_STRIPE;
+  constexpr bool needP = FK == FK_STRIPE || FK == FK_ARRAY_STRIPE;
+  const cx<T> z0 = {(T)0, (T)0};
+  T sv[HB], nv[HB], pv[HB];
+  cx<T> ta[HB], da[HB], tb[HB];
+  auto load_half = [&](int h) {
+#pragma unroll
+    for (int q = 0; q < HB; ++q) {
+      const int ky = t + NT * (h + q);
+      const size_t idx = (size_t)kxc * NY + ky;
+      sv[q] = a.sc[idx];
+      nv[q] = needNb ? a.nbA[idx] : (T)0;
+      pv[q] = needP ? a.pst[ky] : (T)0;
+      ta[q] = hasA ? ((const cx<T>*)a.tA)[idx] : z0;
+      da[q] = hasB ? ((const cx<T>*)a.dA)[idx] : z0;
+      tb[q] = hasB ? ((const cx<T>*)a.tB)[idx] : z0;
+    }
+  };
 
   if constexpr (MODE == COL_INV_IN) {
 #pragma unroll
@@ -486,6 +530,7 @@ __global__ __launch_bounds__(TC * (NY / kE), kMinWaves) void col_kernel(SweepArg
         reg[q] = spec[(size_t)ky * nh + kxc];
       }
     }
+    if constexpr (LTW) __syncthreads();
   } else {
     for (int e = tid * EPC; e < TC * NY; e += blockDim.x * EPC) {
       const int yb = e / TRTC, w = e - yb * TRTC;
@@ -553,10 +598,6 @@ __global__ __launch_bounds__(TC * (NY / kE), kMinWaves) void col_kernel(SweepArg
     k.nxr = (T)a.nx;
     k.fk = a.fk;
     k.store_first = store_first;
-    constexpr bool hasA = FK != FK_NONE;
-    constexpr bool hasB = FK == FK_ARRAY_STRIPE;
-    constexpr bool needNb = FK == FK_ARRAY || FK == FK_ARRAY_STRIPE;
-    constexpr bool needP = FK == FK_STRIPE || FK == FK_ARRAY_STRIPE;
     const cx<T> z = {(T)0, (T)0};
     // the k_x = nx/2 half of the packed column (its own state)
     if (packed) {
@@ -570,25 +611,12 @@ __global__ __launch_bounds__(TC * (NY / kE), kMinWaves) void col_kernel(SweepArg
                              hasB ? ((cx<T>*)a.tB)[idx] : z);
       }
     }
-    // this column: loads batched by quarters, then the updates
-    constexpr int QB = kE / 4;
+    // this column, in two batches of loads
 #pragma unroll
-    for (int h = 0; h < kE; h += QB) {
-      T sv[QB], nv[QB], pv[QB];
-      cx<T> ta[QB], da[QB], tb[QB];
+    for (int h = 0; h < kE; h += HB) {
+      load_half(h);
 #pragma unroll
-      for (int q = 0; q < QB; ++q) {
-        const int ky = t + NT * (h + q);
-        const size_t idx = (size_t)kxc * NY + ky;
-        sv[q] = a.sc[idx];
-        nv[q] = needNb ? a.nbA[idx] : (T)0;
-        pv[q] = needP ? a.pst[ky] : (T)0;
-        ta[q] = hasA ? ((const cx<T>*)a.tA)[idx] : z;
-        da[q] = hasB ? ((const cx<T>*)a.dA)[idx] : z;
-        tb[q] = hasB ? ((const cx<T>*)a.tB)[idx] : z;
-      }
-#pragma unroll
-      for (int q = 0; q < QB; ++q) {
+      for (int q = 0; q < HB; ++q) {
         const int ky = t + NT * (h + q);
         const size_t idx = (size_t)kxc * NY + ky;
         reg[h + q] = chain_mode<T, FK>(a, k, kxc, ky, idx, reg[h + q], sv[q], nv[q], pv[q],

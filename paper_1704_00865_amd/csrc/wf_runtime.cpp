@@ -422,8 +422,10 @@ wf_status solve_t(Ctx* c, const wf_inputs* in, const wf_schedule* s, const void*
   const bool prof = c->profiling != 0;
   if (prof && (int)c->prof_ev.size() < kProfSlots) {
     for (int i = (int)c->prof_ev.size(); i < kProfSlots; ++i) {
+      // timing-only events: no system-scope fence, which would flush caches
+      // and lengthen the measured kernel
       hipEvent_t e;
-      WF_TRY(hipEventCreate(&e));
+      WF_TRY(hipEventCreateWithFlags(&e, hipEventDisableSystemFence));
       c->prof_ev.push_back(e);
     }
   }
