@@ -138,6 +138,18 @@ wf_status wf_solve(void* ctx, const wf_inputs* in, const wf_schedule* sch,
                    const void* s_init, void* s_out, wf_report* rep,
                    double* trace, hipStream_t stream);
 
+/* Approximate inverse-noise weighting N^-1 d (Section 4): the Wiener filter
+ * with a small flat signal covariance S = alpha I gives
+ * N^-1 d ~= alpha^-1 [alpha I (alpha I + N)^-1 d], with relative error of
+ * order alpha / (smallest eigenvalue of N).  in->s_k is ignored; masked
+ * pixels come out as 0 (their inverse variance).  s_init, if given, is a
+ * warm start of the signal-side field alpha (alpha + N)^-1 d.  Other
+ * arguments, outputs and errors as for wf_solve; out receives the weighted
+ * map. */
+wf_status wf_inverse_noise_weight(void* ctx, const wf_inputs* in, double alpha,
+                                  const wf_schedule* sch, const void* s_init, void* out,
+                                  wf_report* rep, double* trace, hipStream_t stream);
+
 /* Unnormalised 2-D real-to-complex FFT with the solver's own kernels:
  * x [ny*nx] real -> X [ny*(nx/2+1)] complex (interleaved re, im), numpy rfft2
  * layout and sign (X_k = sum_p x_p exp(-2 pi i k.p/n)).  DEVICE pointers. */

@@ -39,6 +39,7 @@ from .messenger import (  # noqa: F401
     cooling_ramp,
     diagnostics,
     init_state,
+    inverse_noise_weight,
     joint_objective,
     setup,
     solve,

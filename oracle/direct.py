@@ -137,3 +137,15 @@ def wiener_stationary(problem) -> np.ndarray:
         N[:, 0] += nx * np.asarray(problem.p_stripe, dtype=np.float64)
     dk = np.fft.rfft2(np.asarray(problem.d, dtype=np.float64), norm="ortho")
     return np.fft.irfft2(S / (S + N) * dk, s=(ny, nx), norm="ortho")
+
+
+def inverse_noise_dense(problem) -> np.ndarray:
+    """N^-1 d with N^-1 zero on masked pixels: P^T (P N P^T)^-1 P d (the map
+    that Section 4's small-alpha Wiener filter approximates)."""
+    _, N = dense_covariances(problem)
+    P = observed_index(problem)
+    b = np.asarray(problem.d, dtype=np.float64).ravel()[P]
+    cf = sla.cho_factor(N[np.ix_(P, P)], lower=True)
+    out = np.zeros(problem.d.size)
+    out[P] = sla.cho_solve(cf, b)
+    return out.reshape(problem.d.shape)

@@ -381,3 +381,15 @@ def rfft2_of(u):
 
 def irfft2_of(uk, shape):
     return irfft2u(uk, shape)
+
+
+def inverse_noise_weight(problem, alpha: float, schedule, **kw) -> Result:
+    """Section 4: N^-1 d ~= alpha^-1 [alpha I (alpha I + N)^-1 d].  Runs the
+    messenger iteration with the flat signal covariance S = alpha I and
+    returns the result divided by alpha in ``Result.s``."""
+    import copy
+    q = copy.copy(problem)
+    q.s_k = np.full_like(np.asarray(problem.s_k, dtype=np.float64), float(alpha))
+    res = solve(q, schedule, **kw)
+    res.s = res.s / alpha
+    return res

@@ -68,7 +68,7 @@ class _Report(ctypes.Structure):
 
 EXPORTS = ("wf_ctx_create", "wf_ctx_destroy", "wf_schedule_default", "wf_solve", "wf_rfft2",
            "wf_irfft2", "wf_ctx_set_profiling", "wf_supported", "wf_strerror", "wf_tile_count",
-           "wf_ctx_set_tile", "wf_ctx_get_tile")
+           "wf_ctx_set_tile", "wf_ctx_get_tile", "wf_inverse_noise_weight")
 
 
 def load():
@@ -91,6 +91,11 @@ def load():
     lib.wf_solve.argtypes = [vp, ctypes.POINTER(_Inputs), ctypes.POINTER(_Schedule), vp, vp,
                              ctypes.POINTER(_Report), ctypes.POINTER(ctypes.c_double), vp]
     lib.wf_solve.restype = i32
+    lib.wf_inverse_noise_weight.argtypes = [vp, ctypes.POINTER(_Inputs), ctypes.c_double,
+                                            ctypes.POINTER(_Schedule), vp, vp,
+                                            ctypes.POINTER(_Report),
+                                            ctypes.POINTER(ctypes.c_double), vp]
+    lib.wf_inverse_noise_weight.restype = i32
     lib.wf_rfft2.argtypes = [vp, vp, vp, vp]
     lib.wf_rfft2.restype = i32
     lib.wf_irfft2.argtypes = [vp, vp, vp, vp]
@@ -249,19 +254,50 @@ class Context:
                       p_oof.data_ptr() if p_oof is not None else None,
                       p_stripe.data_ptr() if p_stripe is not None else None,
                       mask.data_ptr() if mask is not None else None)
+        return self._call(lib.wf_solve, "wf_solve", inp, schedule, s_init, out)
+
+    def inverse_noise_weight(self, d, n_pix, p_oof=None, p_stripe=None, mask=None, *,
+                             alpha: float, schedule: Schedule = Schedule(), s_init=None,
+                             out=None):
+        """Approximate N^-1 d as alpha^-1 S (S + N)^-1 d with S = alpha I
+        (Section 4).  Returns (weighted map, report dict, trace array)."""
+        import torch
+        lib = load()
+        ny, nx = self.ny, self.nx
+        nh = nx // 2 + 1
+        self._check(d, (ny, nx), "d")
+        self._check(n_pix, (ny, nx), "n_pix")
+        self._check(p_oof, (ny, nh), "p_oof")
+        self._check(p_stripe, (ny,), "p_stripe")
+        self._check(mask, (ny, nx), "mask", torch.uint8)
+        self._check(s_init, (ny, nx), "s_init")
+        if out is None:
+            out = torch.empty((ny, nx), dtype=self.dtype, device=self.device)
+        self._check(out, (ny, nx), "out")
+        inp = _Inputs(d.data_ptr(), None, n_pix.data_ptr(),
+                      p_oof.data_ptr() if p_oof is not None else None,
+                      p_stripe.data_ptr() if p_stripe is not None else None,
+                      mask.data_ptr() if mask is not None else None)
+
+        def call(h, i, sch, si, o, rep, tr, st):
+            return lib.wf_inverse_noise_weight(h, i, ctypes.c_double(alpha), sch, si, o, rep, tr, st)
+        return self._call(call, "wf_inverse_noise_weight", inp, schedule, s_init, out)
+
+    def _call(self, fn, what, inp, schedule, s_init, out):
+        import torch
         sch, keep = schedule._c()
         nrec = -(-schedule.max_sweeps // schedule.monitor_every)
         trace = np.zeros((nrec, 5), dtype=np.float64)
         rep = _Report()
         with torch.cuda.device(self.device):
-            st = lib.wf_solve(self._h, ctypes.byref(inp), ctypes.byref(sch),
-                              s_init.data_ptr() if s_init is not None else None,
-                              out.data_ptr(), ctypes.byref(rep),
-                              trace.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
-                              _stream_ptr(torch, self.device))
+            st = fn(self._h, ctypes.byref(inp), ctypes.byref(sch),
+                    s_init.data_ptr() if s_init is not None else None,
+                    out.data_ptr(), ctypes.byref(rep),
+                    trace.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                    _stream_ptr(torch, self.device))
         del keep
         if st < 0:
-            raise WFError(st, "wf_solve")
+            raise WFError(st, what)
         report = dict(status=STATUS[st], sweeps=rep.sweeps, n_records=rep.n_records,
                       n_levels=rep.n_levels, lam=rep.lam, rho=rep.rho, rho_mask=rep.rho_mask,
                       dd2=rep.dd2, d2=rep.d2, tau=list(rep.tau), phi=rep.phi,

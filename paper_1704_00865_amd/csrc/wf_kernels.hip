@@ -342,12 +342,14 @@ __global__ __launch_bounds__((RW / 2) * (NX / kE), kMinWaves) void row_kernel(Sw
       }
       return;
     } else {
-      // white-level update, data and coefficients loaded in two batches
+      // white-level update, data and coefficients loaded in batches (two for
+      // float32, four for float64, to stay within the register budget)
+      constexpr int QB = sizeof(T) == 8 ? kE / 4 : kE / 2;
 #pragma unroll
-      for (int h = 0; h < kE; h += kE / 2) {
-        T dv0[kE / 2], dv1[kE / 2], nb0[kE / 2], nb1[kE / 2];
+      for (int h = 0; h < kE; h += QB) {
+        T dv0[QB], dv1[QB], nb0[QB], nb1[QB];
 #pragma unroll
-        for (int q = 0; q < kE / 2; ++q) {
+        for (int q = 0; q < QB; ++q) {
           const size_t i0 = (size_t)ya * NX + t + NT * (h + q);
           dv0[q] = a.d[i0];
           dv1[q] = a.d[i0 + NX];
@@ -355,7 +357,7 @@ __global__ __launch_bounds__((RW / 2) * (NX / kE), kMinWaves) void row_kernel(Sw
           nb1[q] = a.nbar2[i0 + NX];
         }
 #pragma unroll
-        for (int q = 0; q < kE / 2; ++q) {
+        for (int q = 0; q < QB; ++q) {
           const T d1a = reg[h + q].re * sc, d1b = reg[h + q].im * sc;
           reg[h + q] = cx<T>{white_update<T>(dv0[q], nb0[q], d1a, lt),
                              white_update<T>(dv1[q], nb1[q], d1b, lt)};
@@ -492,8 +494,9 @@ __global__ __launch_bounds__(TC * (NY / kE), kMinWaves) void col_kernel(SweepArg
   }
   const cx<T>* tw = LTW ? (const cx<T>*)twl : twg;
 
-  // per-mode state and coefficients of this column, loaded in two batches
-  constexpr int HB = kE / 2;
+  // per-mode state and coefficients of this column, loaded in batches (two
+  // for float32, four for float64)
+  constexpr int HB = sizeof(T) == 8 ? kE / 4 : kE / 2;
   constexpr bool hasA = FK != FK_NONE;
   constexpr bool hasB = FK == FK_ARRAY_STRIPE;
   constexpr bool needNb = FK == FK_ARRAY || FK == FK_ARRAY_STRIPE;
@@ -611,7 +614,7 @@ __global__ __launch_bounds__(TC * (NY / kE), kMinWaves) void col_kernel(SweepArg
                              hasB ? ((cx<T>*)a.tB)[idx] : z);
       }
     }
-    // this column, in two batches of loads
+    // this column, in batches of loads
 #pragma unroll
     for (int h = 0; h < kE; h += HB) {
       load_half(h);
@@ -809,6 +812,21 @@ __global__ __launch_bounds__(kTRM * (NX / kE)) void mon_row_kernel(MonArgs<T> m,
     m.part[2 * band] = a_dd;
     m.part[2 * band + 1] = a_mx;
   }
+}
+
+// fill / scale helpers for the inverse-noise weighting (S = alpha I)
+template <class T>
+__global__ __launch_bounds__(256) void fill_kernel(T* __restrict__ x, int64_t n, double v) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    x[i] = (T)v;
+}
+
+template <class T>
+__global__ __launch_bounds__(256) void scale_kernel(T* __restrict__ x, int64_t n, double f) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    x[i] = (T)((double)x[i] * f);
 }
 
 // One block: fixed-order reduction of the monitor partials, then the cooling

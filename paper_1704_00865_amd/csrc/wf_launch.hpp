@@ -36,4 +36,9 @@ hipError_t launch_prep(const T* npix, const uint8_t* mask, int ny, int nx, doubl
                        const T* sk, const T* poof, const T* pst, const PrepSpecArgs& pa, T* sc, T* nbA,
                        T* sy, T* sig, hipStream_t st);
 
+template <class T>
+hipError_t launch_fill(T* x, int64_t n, double v, hipStream_t st);
+template <class T>
+hipError_t launch_scale(T* x, int64_t n, double f, hipStream_t st);
+
 }  // namespace wf

@@ -57,6 +57,7 @@ struct Ctx {
   int lam_cap = 0;
   double* trace = nullptr;
   int trace_cap = 0;
+  void* alpha_sk = nullptr;  // flat signal spectrum for the inverse-noise weighting
   DevSched* h_ring = nullptr;  // pinned
   double* h_stats = nullptr;   // pinned
   hipEvent_t ev_ring[kRing] = {};
@@ -96,7 +97,8 @@ void make_table(std::vector<T>& out, int n) {
 
 void free_ctx(Ctx* c) {
   void* bufs[] = {c->B, c->tA, c->dA, c->tB, c->sc, c->nbA, c->sy, c->sig, c->nbar2, c->twx, c->twy,
-                  c->twx_d, c->twy_d, c->Mx, c->My, c->part, c->stats, c->sch, c->lam, c->trace};
+                  c->twx_d, c->twy_d, c->Mx, c->My, c->part, c->stats, c->sch, c->lam, c->trace,
+                  c->alpha_sk};
   for (void* p : bufs)
     if (p) (void)hipFree(p);
   if (c->h_ring) (void)hipHostFree(c->h_ring);
@@ -565,6 +567,34 @@ wf_status wf_solve(void* ctx, const wf_inputs* in, const wf_schedule* sch, const
   if (hipGetDevice(&dev) != hipSuccess || dev != c->device) return WF_EINVAL;
   if (c->prec == WF_F64) return solve_t<double>(c, in, sch, s_init, s_out, rep, trace, stream);
   return solve_t<float>(c, in, sch, s_init, s_out, rep, trace, stream);
+}
+
+wf_status wf_inverse_noise_weight(void* ctx, const wf_inputs* in, double alpha,
+                                  const wf_schedule* sch, const void* s_init, void* out,
+                                  wf_report* rep, double* trace, hipStream_t stream) {
+  Ctx* c = (Ctx*)ctx;
+  if (!c || !in || !sch || !out || !in->d || !in->n_pix) return WF_EINVAL;
+  if (!(alpha > 0) || !std::isfinite(alpha)) return WF_EINVAL;
+  const int64_t nmodes = (int64_t)c->ny * c->nh;
+  if (!c->alpha_sk) {
+    wf_status as = alloc(&c->alpha_sk, (size_t)nmodes * c->esz);
+    if (as != WF_OK) return as;
+  }
+  wf_inputs w = *in;
+  w.s_k = c->alpha_sk;
+  const int64_t npix = (int64_t)c->ny * c->nx;
+  wf_status st;
+  if (c->prec == WF_F64) {
+    WF_TRY(launch_fill<double>((double*)c->alpha_sk, nmodes, alpha, stream));
+    st = wf_solve(ctx, &w, sch, s_init, out, rep, trace, stream);
+    if (st >= 0) WF_TRY(launch_scale<double>((double*)out, npix, 1.0 / alpha, stream));
+  } else {
+    WF_TRY(launch_fill<float>((float*)c->alpha_sk, nmodes, alpha, stream));
+    st = wf_solve(ctx, &w, sch, s_init, out, rep, trace, stream);
+    if (st >= 0) WF_TRY(launch_scale<float>((float*)out, npix, 1.0 / alpha, stream));
+  }
+  if (st >= 0) WF_TRY(hipStreamSynchronize(stream));
+  return st;
 }
 
 wf_status wf_rfft2(void* ctx, const void* x, void* X, hipStream_t stream) {
