@@ -138,6 +138,30 @@ wf_status wf_solve(void* ctx, const wf_inputs* in, const wf_schedule* sch,
                    const void* s_init, void* s_out, wf_report* rep,
                    double* trace, hipStream_t stream);
 
+/* Largest batch wf_solve_batch accepts. */
+#define WF_BATCH_MAX 1024
+
+/* Solve n independent maps with one schedule (Section 2 iteration; the
+ * survey setting of Section 5 filters many maps of a few shapes).  Maps of
+ * equal shape and chain kind share every kernel launch (one grid row per
+ * map); one chunk of monitor_every sweeps of every map plus their monitors
+ * is recorded once as a HIP graph and replayed, and each map keeps its own
+ * device-side cooling schedule and stops on its own.
+ *   ctxs[n]    distinct contexts of one precision on the current device, one
+ *              per map (the context fixes the map's shape and tiling);
+ *   inputs[n]  HOST array of per-map inputs (DEVICE pointers inside);
+ *   sch        one schedule for every map (adaptive or fixed);
+ *   s_out[n]   HOST array of DEVICE output pointers [ny_i*nx_i];
+ *   reps[n]    HOST reports, or NULL.
+ * Zero start only.  Returns the most severe error of any map, else
+ * WF_NOT_CONVERGED if any map ran out of sweeps, else WF_OK; per-map status
+ * is in reps[i].status.  Input errors are found before any sweep runs.
+ * Allocates its per-call device buffers and graph and frees them before it
+ * returns; synchronises stream. */
+wf_status wf_solve_batch(void* const* ctxs, int32_t n, const wf_inputs* inputs,
+                         const wf_schedule* sch, void* const* s_out, wf_report* reps,
+                         hipStream_t stream);
+
 /* Approximate inverse-noise weighting N^-1 d (Section 4): the Wiener filter
  * with a small flat signal covariance S = alpha I gives
  * N^-1 d ~= alpha^-1 [alpha I (alpha I + N)^-1 d], with relative error of

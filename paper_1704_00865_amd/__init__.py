@@ -18,7 +18,7 @@ import numpy as np
 
 __all__ = [
     "load", "Context", "Schedule", "solve", "rfft2", "irfft2", "strerror",
-    "WFError", "STATUS", "CHAINS",
+    "WFError", "STATUS", "CHAINS", "solve_batch",
 ]
 
 _LIB_PATH = os.environ.get("WF_LIBRARY") or os.path.join(
@@ -68,7 +68,7 @@ class _Report(ctypes.Structure):
 
 EXPORTS = ("wf_ctx_create", "wf_ctx_destroy", "wf_schedule_default", "wf_solve", "wf_rfft2",
            "wf_irfft2", "wf_ctx_set_profiling", "wf_supported", "wf_strerror", "wf_tile_count",
-           "wf_ctx_set_tile", "wf_ctx_get_tile", "wf_inverse_noise_weight")
+           "wf_ctx_set_tile", "wf_ctx_get_tile", "wf_inverse_noise_weight", "wf_solve_batch")
 
 
 def load():
@@ -96,6 +96,10 @@ def load():
                                             ctypes.POINTER(_Report),
                                             ctypes.POINTER(ctypes.c_double), vp]
     lib.wf_inverse_noise_weight.restype = i32
+    lib.wf_solve_batch.argtypes = [ctypes.POINTER(vp), i32, ctypes.POINTER(_Inputs),
+                                   ctypes.POINTER(_Schedule), ctypes.POINTER(vp),
+                                   ctypes.POINTER(_Report), vp]
+    lib.wf_solve_batch.restype = i32
     lib.wf_rfft2.argtypes = [vp, vp, vp, vp]
     lib.wf_rfft2.restype = i32
     lib.wf_irfft2.argtypes = [vp, vp, vp, vp]
@@ -167,6 +171,19 @@ class Schedule:
         s.chain = CHAINS[self.chain]
         s.stop_full = 1 if self.stop_full else 0
         return s, keep
+
+
+def _inputs(d, s_k, n_pix, p_oof, p_stripe, mask):
+    def ptr(t):
+        return t.data_ptr() if t is not None else None
+    return _Inputs(ptr(d), ptr(s_k), ptr(n_pix), ptr(p_oof), ptr(p_stripe), ptr(mask))
+
+
+def _report(rep) -> dict:
+    return dict(status=STATUS[rep.status], sweeps=rep.sweeps, n_records=rep.n_records,
+                n_levels=rep.n_levels, lam=rep.lam, rho=rep.rho, rho_mask=rep.rho_mask,
+                dd2=rep.dd2, d2=rep.d2, tau=list(rep.tau), phi=rep.phi,
+                kernel_ms=list(rep.kernel_ms), kernel_launches=list(rep.kernel_launches))
 
 
 def _stream_ptr(torch, device):
@@ -250,10 +267,7 @@ class Context:
         if out is None:
             out = torch.empty((ny, nx), dtype=self.dtype, device=self.device)
         self._check(out, (ny, nx), "out")
-        inp = _Inputs(d.data_ptr(), s_k.data_ptr(), n_pix.data_ptr(),
-                      p_oof.data_ptr() if p_oof is not None else None,
-                      p_stripe.data_ptr() if p_stripe is not None else None,
-                      mask.data_ptr() if mask is not None else None)
+        inp = _inputs(d, s_k, n_pix, p_oof, p_stripe, mask)
         return self._call(lib.wf_solve, "wf_solve", inp, schedule, s_init, out)
 
     def inverse_noise_weight(self, d, n_pix, p_oof=None, p_stripe=None, mask=None, *,
@@ -298,11 +312,7 @@ class Context:
         del keep
         if st < 0:
             raise WFError(st, what)
-        report = dict(status=STATUS[st], sweeps=rep.sweeps, n_records=rep.n_records,
-                      n_levels=rep.n_levels, lam=rep.lam, rho=rep.rho, rho_mask=rep.rho_mask,
-                      dd2=rep.dd2, d2=rep.d2, tau=list(rep.tau), phi=rep.phi,
-                      kernel_ms=list(rep.kernel_ms), kernel_launches=list(rep.kernel_launches))
-        return out, report, trace[: rep.n_records]
+        return out, _report(rep), trace[: rep.n_records]
 
     def rfft2(self, x):
         import torch
@@ -337,6 +347,54 @@ def solve(d, s_k, n_pix, p_oof=None, p_stripe=None, mask=None, *, schedule=Sched
         return ctx.solve(d, s_k, n_pix, p_oof, p_stripe, mask, schedule=schedule, s_init=s_init)
     finally:
         ctx.close()
+
+
+def solve_batch(contexts, problems, *, schedule: Schedule = Schedule(), outs=None):
+    """Solve many maps at once (``wf_solve_batch``).  contexts: one distinct
+    ``Context`` per map (same precision and device); problems: per map a dict
+    with keys d, s_k, n_pix and optionally p_oof, p_stripe, mask (device
+    tensors checked like ``Context.solve``).  Returns (list of maps, list of
+    report dicts).  Maps of one shape share their kernel launches; one chunk
+    of sweeps is replayed as a HIP graph."""
+    import torch
+    lib = load()
+    n = len(contexts)
+    if n != len(problems) or n < 1:
+        raise ValueError("need one problem per context")
+    if outs is None:
+        outs = [None] * n
+    inps = (_Inputs * n)()
+    handles = (ctypes.c_void_p * n)()
+    optrs = (ctypes.c_void_p * n)()
+    res = []
+    for i, (ctx, pb) in enumerate(zip(contexts, problems)):
+        ny, nx = ctx.ny, ctx.nx
+        nh = nx // 2 + 1
+        ctx._check(pb["d"], (ny, nx), "d")
+        ctx._check(pb["s_k"], (ny, nh), "s_k")
+        ctx._check(pb["n_pix"], (ny, nx), "n_pix")
+        ctx._check(pb.get("p_oof"), (ny, nh), "p_oof")
+        ctx._check(pb.get("p_stripe"), (ny,), "p_stripe")
+        ctx._check(pb.get("mask"), (ny, nx), "mask", torch.uint8)
+        o = outs[i]
+        if o is None:
+            o = torch.empty((ny, nx), dtype=ctx.dtype, device=ctx.device)
+        ctx._check(o, (ny, nx), "out")
+        res.append(o)
+        inps[i] = _inputs(pb["d"], pb["s_k"], pb["n_pix"], pb.get("p_oof"),
+                          pb.get("p_stripe"), pb.get("mask"))
+        handles[i] = ctx._h
+        optrs[i] = o.data_ptr()
+    sch, keep = schedule._c()
+    reps = (_Report * n)()
+    dev = contexts[0].device
+    with torch.cuda.device(dev):
+        st = lib.wf_solve_batch(handles, n, inps, ctypes.byref(sch), optrs, reps,
+                                _stream_ptr(torch, dev))
+    del keep
+    if st < 0:
+        raise WFError(st, "wf_solve_batch")
+    return res, [_report(r) for r in reps]
 
 
 def rfft2(x):

@@ -1,8 +1,9 @@
 // Workgroup FFTs for gfx950: radix-16/8/4 Stockham passes with the data in
 // registers and one LDS exchange between passes.
 //
-// A transform of length N (power of two, 64..4096) is spread over NT = N/16
-// threads that each hold E = 16 complex values.  Register q of thread t holds
+// A transform of length N (a power of two from 64 to 4096, or 3 times one:
+// 384, 768, 1536) is spread over NT = N/E threads that each hold E complex
+// values (E = 16, or 24 when N has a factor 3).  Register q of thread t holds
 // element t + NT*q both before the first pass and after the last one (natural
 // order), so a transform can be followed by per-element work and by another
 // transform without any reshuffle, and its first loads and last stores are
@@ -10,7 +11,7 @@
 // computes, for butterfly i in [0, N/R):
 //     u_m = x[i + m N/R] * w_{pR}^{m (i mod p)},  U = DFT_R(u),
 //     y[(i - i mod p) R + (i mod p) + m p] = U_m,
-// the autosorting Stockham form.  Twiddles w_N^j come from a table built in
+// the autosorting Stockham form (radix 16, 8, 4, 3).  Twiddles w_N^j come from a table built in
 // double precision on the host and rounded once (no device sin/cos).
 #pragma once
 
@@ -123,9 +124,23 @@ __device__ __forceinline__ void dft16(cx<T>* u) {
   }
 }
 
+// 3-point DFT: w_3 = -1/2 -+ i sqrt(3)/2 (minus for the forward transform)
+template <class T, bool INV>
+__device__ __forceinline__ void dft3(cx<T>* u) {
+  const T c = (T)-0.5, s = (T)(INV ? 0.86602540378443864676 : -0.86602540378443864676);
+  const cx<T> a0 = u[0], a1 = u[1], a2 = u[2];
+  const cx<T> sm = a1 + a2, df = a1 - a2;
+  const cx<T> m = {a0.re + c * sm.re, a0.im + c * sm.im};
+  const cx<T> r = {-s * df.im, s * df.re};  // i s (a1 - a2)
+  u[0] = a0 + sm;
+  u[1] = m + r;
+  u[2] = m - r;
+}
+
 template <class T, int R, bool INV>
 __device__ __forceinline__ void dft(cx<T>* u) {
   if constexpr (R == 2) dft2<T, INV>(u);
+  else if constexpr (R == 3) dft3<T, INV>(u);
   else if constexpr (R == 4) dft4<T, INV>(u);
   else if constexpr (R == 8) dft8<T, INV>(u);
   else if constexpr (R == 16) dft16<T, INV>(u);
@@ -139,26 +154,39 @@ struct padded {
   static constexpr int value = N + N / 16;
 };
 
-// radix plan: 16 * R1 * R2 = N
+// complex values held by each thread: 16 for powers of two, 24 for lengths
+// with a factor 3 (so that both radix 8 and radix 3 divide it)
+template <int N>
+struct elems {
+  static constexpr int value = (N % 3 == 0) ? 24 : 16;
+};
+
+// radix plan R0 * R1 * R2 * R3 = N (1 = no pass); a radix-3 pass comes last
+// so every earlier span is a power of two
 template <int N>
 struct plan;
-template <> struct plan<64> { static constexpr int r1 = 4, r2 = 1; };
-template <> struct plan<128> { static constexpr int r1 = 8, r2 = 1; };
-template <> struct plan<256> { static constexpr int r1 = 16, r2 = 1; };
-template <> struct plan<512> { static constexpr int r1 = 8, r2 = 4; };
-template <> struct plan<1024> { static constexpr int r1 = 16, r2 = 4; };
-template <> struct plan<2048> { static constexpr int r1 = 16, r2 = 8; };
-template <> struct plan<4096> { static constexpr int r1 = 16, r2 = 16; };
+template <> struct plan<64> { static constexpr int r[4] = {16, 4, 1, 1}; };
+template <> struct plan<128> { static constexpr int r[4] = {16, 8, 1, 1}; };
+template <> struct plan<256> { static constexpr int r[4] = {16, 16, 1, 1}; };
+template <> struct plan<512> { static constexpr int r[4] = {16, 8, 4, 1}; };
+template <> struct plan<1024> { static constexpr int r[4] = {16, 16, 4, 1}; };
+template <> struct plan<2048> { static constexpr int r[4] = {16, 16, 8, 1}; };
+template <> struct plan<4096> { static constexpr int r[4] = {16, 16, 16, 1}; };
+template <> struct plan<384> { static constexpr int r[4] = {8, 4, 4, 3}; };
+template <> struct plan<768> { static constexpr int r[4] = {8, 8, 4, 3}; };
+template <> struct plan<1536> { static constexpr int r[4] = {8, 8, 8, 3}; };
 
-constexpr int kE = 16;  // complex values held by each thread
+constexpr int kE = 16;  // values per thread for power-of-two lengths
 
 // One Stockham pass.  reg: the thread's E values; lds: this transform's
 // padded exchange buffer; tw: w_N^j table (forward sign).
 template <class T, int N, int R, int P, bool INV, bool LAST>
 __device__ __forceinline__ void stockham_pass(cx<T>* reg, cx<T>* lds, int t,
                                               const cx<T>* __restrict__ tw) {
-  constexpr int NT = N / kE;
-  constexpr int NB = kE / R;
+  constexpr int E = elems<N>::value;
+  constexpr int NT = N / E;
+  constexpr int NB = E / R;
+  static_assert(E % R == 0, "radix must divide the values per thread");
 #pragma unroll
   for (int b = 0; b < NB; ++b) {
     const int i = t + b * NT;
@@ -188,7 +216,7 @@ __device__ __forceinline__ void stockham_pass(cx<T>* reg, cx<T>* lds, int t,
   if constexpr (!LAST) {
     __syncthreads();
 #pragma unroll
-    for (int q = 0; q < kE; ++q) reg[q] = lds[lpad(t + NT * q)];
+    for (int q = 0; q < E; ++q) reg[q] = lds[lpad(t + NT * q)];
     __syncthreads();
   }
 }
@@ -198,14 +226,20 @@ __device__ __forceinline__ void stockham_pass(cx<T>* reg, cx<T>* lds, int t,
 // transform and must not be in use by the caller.
 template <class T, int N, bool INV>
 __device__ __forceinline__ void fft(cx<T>* reg, cx<T>* lds, int t, const cx<T>* __restrict__ tw) {
-  constexpr int R1 = plan<N>::r1, R2 = plan<N>::r2;
+  constexpr int R0 = plan<N>::r[0], R1 = plan<N>::r[1], R2 = plan<N>::r[2], R3 = plan<N>::r[3];
+  static_assert(R0 * R1 * R2 * R3 == N, "radix plan must multiply to N");
   if constexpr (R2 == 1) {
-    stockham_pass<T, N, 16, 1, INV, false>(reg, lds, t, tw);
-    stockham_pass<T, N, R1, 16, INV, true>(reg, lds, t, tw);
+    stockham_pass<T, N, R0, 1, INV, false>(reg, lds, t, tw);
+    stockham_pass<T, N, R1, R0, INV, true>(reg, lds, t, tw);
+  } else if constexpr (R3 == 1) {
+    stockham_pass<T, N, R0, 1, INV, false>(reg, lds, t, tw);
+    stockham_pass<T, N, R1, R0, INV, false>(reg, lds, t, tw);
+    stockham_pass<T, N, R2, R0 * R1, INV, true>(reg, lds, t, tw);
   } else {
-    stockham_pass<T, N, 16, 1, INV, false>(reg, lds, t, tw);
-    stockham_pass<T, N, R1, 16, INV, false>(reg, lds, t, tw);
-    stockham_pass<T, N, R2, 16 * R1, INV, true>(reg, lds, t, tw);
+    stockham_pass<T, N, R0, 1, INV, false>(reg, lds, t, tw);
+    stockham_pass<T, N, R1, R0, INV, false>(reg, lds, t, tw);
+    stockham_pass<T, N, R2, R0 * R1, INV, false>(reg, lds, t, tw);
+    stockham_pass<T, N, R3, R0 * R1 * R2, INV, true>(reg, lds, t, tw);
   }
 }
 

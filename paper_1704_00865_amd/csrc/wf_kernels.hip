@@ -261,14 +261,19 @@ constexpr bool lds_twiddles() {
 }
 
 // at least 2 waves per SIMD so that two blocks share a CU and one
-// block's memory phase overlaps another's FFT
-constexpr int kMinWaves = 2;
+// block's memory phase overlaps another's FFT; float64 transforms with 24
+// values per thread need the whole register file of one wave instead
+template <class T, int N>
+constexpr int min_waves() {
+  return (sizeof(T) == 8 && elems<N>::value == 24) ? 1 : 2;
+}
 
 template <class T, int NX, int TR, int TC, int RW, int MODE>
-__global__ __launch_bounds__((RW / 2) * (NX / kE), kMinWaves) void row_kernel(SweepArgs<T> a, int k_local,
-                                                                   const T* __restrict__ xin,
-                                                                   T* __restrict__ xout) {
-  constexpr int NT = NX / kE;
+__global__ __launch_bounds__((RW / 2) * (NX / elems<NX>::value), (min_waves<T, NX>())) void row_kernel(const SweepArgs<T>* __restrict__ argv, int k_local,
+    const T* __restrict__ xin, T* __restrict__ xout) {
+  const SweepArgs<T>& a = argv[blockIdx.y];  // one map per grid row
+  constexpr int E = elems<NX>::value;
+  constexpr int NT = NX / E;
   constexpr int RP = RW / 2;
   constexpr int KPC = NX / 2;                 // packed half width
   constexpr int SUB = RW * KPC;               // complex values of this block's rows
@@ -295,7 +300,7 @@ __global__ __launch_bounds__((RW / 2) * (NX / kE), kMinWaves) void row_kernel(Sw
   const cx<T>* twg = (const cx<T>*)a.twx;
   const int p = tid / NT, t = tid - p * NT;
   const int ya = y0 + 2 * p;
-  cx<T> reg[kE];
+  cx<T> reg[E];
   if constexpr (LTW) {
     for (int j = tid; j < NX; j += blockDim.x) twl[j] = twg[j];
   }
@@ -310,7 +315,7 @@ __global__ __launch_bounds__((RW / 2) * (NX / kE), kMinWaves) void row_kernel(Sw
     // Z = A + i B for the row pair; A, B Hermitian in k_x; slot 0 packs
     // (re of k_x = 0, re of k_x = nx/2)
 #pragma unroll
-    for (int q = 0; q < kE; ++q) {
+    for (int q = 0; q < E; ++q) {
       const int k = t + NT * q;
       const bool hi = k > NX / 2;
       const int kx = hi ? NX - k : k;
@@ -335,18 +340,18 @@ __global__ __launch_bounds__((RW / 2) * (NX / kE), kMinWaves) void row_kernel(Sw
     const T sc = (T)a.scale;
     if constexpr (MODE == ROW_C2R) {
 #pragma unroll
-      for (int q = 0; q < kE; ++q) {
+      for (int q = 0; q < E; ++q) {
         const size_t i0 = (size_t)ya * NX + t + NT * q;
         xout[i0] = reg[q].re * sc;
         xout[i0 + NX] = reg[q].im * sc;
       }
       return;
     } else {
-      // white-level update, data and coefficients loaded in batches (two for
-      // float32, four for float64, to stay within the register budget)
-      constexpr int QB = sizeof(T) == 8 ? kE / 4 : kE / 2;
+      // white-level update, data and coefficients loaded in batches of 8
+      // (float32) or 4 (float64) values, to stay within the register budget
+      constexpr int QB = sizeof(T) == 8 ? 4 : 8;
 #pragma unroll
-      for (int h = 0; h < kE; h += QB) {
+      for (int h = 0; h < E; h += QB) {
         T dv0[QB], dv1[QB], nb0[QB], nb1[QB];
 #pragma unroll
         for (int q = 0; q < QB; ++q) {
@@ -366,7 +371,7 @@ __global__ __launch_bounds__((RW / 2) * (NX / kE), kMinWaves) void row_kernel(Sw
     }
   } else {  // ROW_R2C
 #pragma unroll
-    for (int q = 0; q < kE; ++q) {
+    for (int q = 0; q < E; ++q) {
       const size_t i0 = (size_t)ya * NX + t + NT * q;
       reg[q] = cx<T>{xin[i0], xin[i0 + NX]};
     }
@@ -374,7 +379,7 @@ __global__ __launch_bounds__((RW / 2) * (NX / kE), kMinWaves) void row_kernel(Sw
   }
   fft<T, NX, false>(reg, lds + p * XS, t, tw);
 #pragma unroll
-  for (int q = 0; q < kE; ++q) lds[p * XS + lpad(t + NT * q)] = reg[q];
+  for (int q = 0; q < E; ++q) lds[p * XS + lpad(t + NT * q)] = reg[q];
   __syncthreads();
   // split Z into the two rows' spectra; write this block's rows, tile order
   for (int e = tid * EPC; e < SUB; e += blockDim.x * EPC) {
@@ -454,10 +459,11 @@ template <class T>
 __device__ __forceinline__ cx<T> cconj(cx<T> v) { return cx<T>{v.re, -v.im}; }
 
 template <class T, int NY, int TR, int TC, int MODE, int FK>
-__global__ __launch_bounds__(TC * (NY / kE), kMinWaves) void col_kernel(SweepArgs<T> a, int k_local,
-                                                             cx<T>* __restrict__ spec,
-                                                             double lam_init) {
-  constexpr int NT = NY / kE;
+__global__ __launch_bounds__(TC * (NY / elems<NY>::value), (min_waves<T, NY>())) void col_kernel(const SweepArgs<T>* __restrict__ argv, int k_local,
+    cx<T>* __restrict__ spec, double lam_init) {
+  const SweepArgs<T>& a = argv[blockIdx.y];  // one map per grid row
+  constexpr int E = elems<NY>::value;
+  constexpr int NT = NY / E;
   constexpr int YS = padded<NY>::value;
   constexpr int TRTC = TR * TC;
   constexpr int EPC = 16 / (2 * (int)sizeof(T));
@@ -488,15 +494,15 @@ __global__ __launch_bounds__(TC * (NY / kE), kMinWaves) void col_kernel(SweepArg
   const int kxn = a.nx / 2;
   cx<T>* gB = (cx<T>*)a.B;
   const cx<T>* twg = (const cx<T>*)a.twy;
-  cx<T> reg[kE];
+  cx<T> reg[E];
   if constexpr (LTW) {
     for (int j = tid; j < NY; j += blockDim.x) twl[j] = twg[j];
   }
   const cx<T>* tw = LTW ? (const cx<T>*)twl : twg;
 
-  // per-mode state and coefficients of this column, loaded in batches (two
-  // for float32, four for float64)
-  constexpr int HB = sizeof(T) == 8 ? kE / 4 : kE / 2;
+  // per-mode state and coefficients of this column, loaded in batches of 8
+  // (float32) or 4 (float64) modes
+  constexpr int HB = sizeof(T) == 8 ? 4 : 8;
   constexpr bool hasA = FK != FK_NONE;
   constexpr bool hasB = FK == FK_ARRAY_STRIPE;
   constexpr bool needNb = FK == FK_ARRAY || FK == FK_ARRAY_STRIPE;
@@ -520,11 +526,11 @@ __global__ __launch_bounds__(TC * (NY / kE), kMinWaves) void col_kernel(SweepArg
 
   if constexpr (MODE == COL_INV_IN) {
 #pragma unroll
-    for (int q = 0; q < kE; ++q) {
+    for (int q = 0; q < E; ++q) {
       const int ky = t + NT * q;
       if (packed) {
         // Hermitian parts of the k_x = 0 and nx/2 columns (irfft2 semantics)
-        const int km = (NY - ky) & (NY - 1);
+        const int km = ky == 0 ? 0 : NY - ky;
         const cx<T> a0 = spec[(size_t)ky * nh], b0 = spec[(size_t)km * nh];
         const cx<T> an = spec[(size_t)ky * nh + kxn], bn = spec[(size_t)km * nh + kxn];
         const cx<T> h0 = cscale(a0 + cconj(b0), (T)0.5), hn = cscale(an + cconj(bn), (T)0.5);
@@ -547,7 +553,7 @@ __global__ __launch_bounds__(TC * (NY / kE), kMinWaves) void col_kernel(SweepArg
     }
     __syncthreads();
 #pragma unroll
-    for (int q = 0; q < kE; ++q) reg[q] = lds[c * YS + lpad(t + NT * q)];
+    for (int q = 0; q < E; ++q) reg[q] = lds[c * YS + lpad(t + NT * q)];
     __syncthreads();
     fft<T, NY, false>(reg, lds + c * YS, t, tw);
   }
@@ -560,15 +566,15 @@ __global__ __launch_bounds__(TC * (NY / kE), kMinWaves) void col_kernel(SweepArg
     if (g == 0) {
       if (packed) {
 #pragma unroll
-        for (int q = 0; q < kE; ++q) lds[lpad(t + NT * q)] = reg[q];
+        for (int q = 0; q < E; ++q) lds[lpad(t + NT * q)] = reg[q];
       }
       __syncthreads();
-      cx<T> cnv[kE];
+      cx<T> cnv[E];
       if (packed) {
 #pragma unroll
-        for (int q = 0; q < kE; ++q) {
+        for (int q = 0; q < E; ++q) {
           const int ky = t + NT * q;
-          const cx<T> zk = reg[q], zm = lds[lpad((NY - ky) & (NY - 1))];
+          const cx<T> zk = reg[q], zm = lds[lpad(ky == 0 ? 0 : NY - ky)];
           reg[q] = cx<T>{(zk.re + zm.re) * (T)0.5, (zk.im - zm.im) * (T)0.5};
           cnv[q] = cx<T>{(zk.im + zm.im) * (T)0.5, (zm.re - zk.re) * (T)0.5};
         }
@@ -576,14 +582,14 @@ __global__ __launch_bounds__(TC * (NY / kE), kMinWaves) void col_kernel(SweepArg
       __syncthreads();
       if (packed) {
 #pragma unroll
-        for (int q = 0; q < kE; ++q) cnl[lpad(t + NT * q)] = cnv[q];
+        for (int q = 0; q < E; ++q) cnl[lpad(t + NT * q)] = cnv[q];
       }
     }
   }
 
   if constexpr (MODE == COL_FWD_OUT) {
 #pragma unroll
-    for (int q = 0; q < kE; ++q) {
+    for (int q = 0; q < E; ++q) {
       const size_t row = (size_t)(t + NT * q) * nh;
       spec[row + kxc] = reg[q];
       if (packed) spec[row + kxn] = cnl[lpad(t + NT * q)];
@@ -604,7 +610,7 @@ __global__ __launch_bounds__(TC * (NY / kE), kMinWaves) void col_kernel(SweepArg
     const cx<T> z = {(T)0, (T)0};
     // the k_x = nx/2 half of the packed column (its own state)
     if (packed) {
-      for (int q = 0; q < kE; ++q) {
+      for (int q = 0; q < E; ++q) {
         const int ky = t + NT * q;
         const size_t idx = (size_t)kxn * NY + ky;
         const int li = lpad(ky);
@@ -616,7 +622,7 @@ __global__ __launch_bounds__(TC * (NY / kE), kMinWaves) void col_kernel(SweepArg
     }
     // this column, in batches of loads
 #pragma unroll
-    for (int h = 0; h < kE; h += HB) {
+    for (int h = 0; h < E; h += HB) {
       load_half(h);
 #pragma unroll
       for (int q = 0; q < HB; ++q) {
@@ -628,7 +634,7 @@ __global__ __launch_bounds__(TC * (NY / kE), kMinWaves) void col_kernel(SweepArg
     }
     if (packed) {
 #pragma unroll
-      for (int q = 0; q < kE; ++q) {
+      for (int q = 0; q < E; ++q) {
         const cx<T> cv = cnl[lpad(t + NT * q)];
         reg[q] = cx<T>{reg[q].re - cv.im, reg[q].im + cv.re};
       }
@@ -644,7 +650,7 @@ __global__ __launch_bounds__(TC * (NY / kE), kMinWaves) void col_kernel(SweepArg
     cx<T>* tB = (cx<T>*)a.tB;
     const T TW0 = (T)(lam_init * a.tauW);
 #pragma unroll
-    for (int q = 0; q < kE; ++q) {
+    for (int q = 0; q < E; ++q) {
       const int ky = t + NT * q;
       cx<T> out[2];
 #pragma unroll
@@ -673,7 +679,7 @@ __global__ __launch_bounds__(TC * (NY / kE), kMinWaves) void col_kernel(SweepArg
   __syncthreads();
   fft<T, NY, true>(reg, lds + c * YS, t, tw);
 #pragma unroll
-  for (int q = 0; q < kE; ++q) lds[c * YS + lpad(t + NT * q)] = reg[q];
+  for (int q = 0; q < E; ++q) lds[c * YS + lpad(t + NT * q)] = reg[q];
   __syncthreads();
   for (int e = tid * EPC; e < TC * NY; e += blockDim.x * EPC) {
     const int yb = e / TRTC, w = e - yb * TRTC;
@@ -701,13 +707,15 @@ __device__ __forceinline__ bool monitor_active(const DevSched* s, double* lam_la
 }
 
 template <class T, int NY>
-__global__ __launch_bounds__(kTCM * (NY / kE)) void mon_col_kernel(MonArgs<T> m, int mode,
-                                                                   double lam_out) {
-  constexpr int NT = NY / kE;
+__global__ __launch_bounds__(kTCM * (NY / elems<NY>::value)) void mon_col_kernel(const MonArgs<T>* __restrict__ argv, int mode) {
+  const MonArgs<T>& m = argv[blockIdx.y];
+  constexpr int E = elems<NY>::value;
+  constexpr int NT = NY / E;
   constexpr int YS = padded<NY>::value;
   constexpr int TRTC = kTRM * kTCM;
   __shared__ cx<double> lds[kTCM * YS];
-  double lamv = lam_out;
+  // residual: lambda of the chunk's last sweep; output: of the last sweep run
+  double lamv = m.sch->lam_last;
   if (mode == MON_RESIDUAL && !monitor_active(m.sch, &lamv, m.lam)) return;
   const int tid = threadIdx.x, g = blockIdx.x, G = m.kpm / kTCM;
   const int c = tid / NT, t = tid - c * NT;
@@ -715,9 +723,9 @@ __global__ __launch_bounds__(kTCM * (NY / kE)) void mon_col_kernel(MonArgs<T> m,
   const bool valid = kx < m.nx / 2 + 1;
   const double Tf = lamv * m.tau_first;
   const cx<T>* tf = (const cx<T>*)m.tfirst;
-  cx<double> rx[kE], ry[kE];
+  cx<double> rx[E], ry[E];
 #pragma unroll
-  for (int q = 0; q < kE; ++q) {
+  for (int q = 0; q < E; ++q) {
     const int ky = t + NT * q;
     const size_t idx = (size_t)kx * NY + ky;
     if (valid) {
@@ -738,7 +746,7 @@ __global__ __launch_bounds__(kTCM * (NY / kE)) void mon_col_kernel(MonArgs<T> m,
     cx<double>* dst = field == 0 ? m.Mx : m.My;
     fft<double, NY, true>(reg, lds + c * YS, t, m.twy);
 #pragma unroll
-    for (int q = 0; q < kE; ++q) lds[c * YS + lpad(t + NT * q)] = reg[q];
+    for (int q = 0; q < E; ++q) lds[c * YS + lpad(t + NT * q)] = reg[q];
     __syncthreads();
     for (int e = tid; e < kTCM * NY; e += blockDim.x) {
       const int yb = e / TRTC, w = e - yb * TRTC;
@@ -750,9 +758,11 @@ __global__ __launch_bounds__(kTCM * (NY / kE)) void mon_col_kernel(MonArgs<T> m,
 }
 
 template <class T, int NX>
-__global__ __launch_bounds__(kTRM * (NX / kE)) void mon_row_kernel(MonArgs<T> m, int mode,
-                                                                   T* __restrict__ s_out) {
-  constexpr int NT = NX / kE;
+__global__ __launch_bounds__(kTRM * (NX / elems<NX>::value)) void mon_row_kernel(const MonArgs<T>* __restrict__ argv, int mode) {
+  const MonArgs<T>& m = argv[blockIdx.y];
+  T* __restrict__ s_out = (T*)m.s_out;
+  constexpr int E = elems<NX>::value;
+  constexpr int NT = NX / E;
   constexpr int KPm = KP<NX, kTCM>::value;
   constexpr int BANDm = kTRM * KPm;
   constexpr int XS = padded<NX>::value;
@@ -770,9 +780,9 @@ __global__ __launch_bounds__(kTRM * (NX / kE)) void mon_row_kernel(MonArgs<T> m,
   }
   __syncthreads();
   const int r = tid / NT, t = tid - r * NT;
-  cx<double> reg[kE];
+  cx<double> reg[E];
 #pragma unroll
-  for (int q = 0; q < kE; ++q) {
+  for (int q = 0; q < E; ++q) {
     const int k = t + NT * q;
     const bool hi = k > NX / 2;
     const int kx = hi ? NX - k : k;
@@ -793,7 +803,7 @@ __global__ __launch_bounds__(kTRM * (NX / kE)) void mon_row_kernel(MonArgs<T> m,
   const int y = band * kTRM + r;
   double a_dd = 0.0, a_mx = 0.0;
 #pragma unroll
-  for (int q = 0; q < kE; ++q) {
+  for (int q = 0; q < E; ++q) {
     const size_t i = (size_t)y * NX + t + NT * q;
     const double xv = reg[q].re * m.scale, yv = reg[q].im * m.scale;
     if (mode == MON_OUTPUT) {
@@ -831,9 +841,14 @@ __global__ __launch_bounds__(256) void scale_kernel(T* __restrict__ x, int64_t n
 
 // One block: fixed-order reduction of the monitor partials, then the cooling
 // schedule (fixed array, or the plateau rule of Section 3.3) and the stop test.
-__global__ __launch_bounds__(256) void controller_kernel(DevSched* s, double* lam,
-                                                         const double* __restrict__ part, int nblk,
-                                                         double* __restrict__ trace) {
+__global__ __launch_bounds__(256) void controller_kernel(const CtrlArgs* __restrict__ argv) {
+  // one block per map
+  const CtrlArgs& ca = argv[blockIdx.x];
+  DevSched* s = ca.sch;
+  double* lam = ca.lam;
+  const double* __restrict__ part = ca.part;
+  const int nblk = ca.nblk;
+  double* __restrict__ trace = ca.trace;
   __shared__ double sh[16];
   if (s->done) return;
   double a = 0.0, b = 0.0;

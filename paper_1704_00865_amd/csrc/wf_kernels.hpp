@@ -94,9 +94,19 @@ struct MonArgs {
   const DevSched* sch;
   const double* lam;
   double* part;         // per-block (sum dd^2, sum masked x^2)
+  void* s_out;          // T [ny][nx]: output of the final (output-mode) pass
   int nx, ny, kpm;      // kpm: padded half width (multiple of kTCM)
   double tau_first;
   double scale;
+};
+
+// per-map arguments of the controller (one block per map)
+struct CtrlArgs {
+  DevSched* sch;
+  double* lam;
+  const double* part;
+  int nblk;
+  double* trace;
 };
 
 }  // namespace wf

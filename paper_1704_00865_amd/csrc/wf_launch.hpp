@@ -15,18 +15,22 @@ constexpr int kNumTiles = 7;
 constexpr int kTileDefault = 1;
 extern const TileCfg kTiles[kNumTiles];
 
+// Every launch covers nmaps maps of one shape and chain kind: argv is a
+// DEVICE array of nmaps argument blocks (blockIdx.y selects one); a / m is a
+// host copy of one of them, for the sizes.
 template <class T>
-hipError_t launch_row(int cfg, int mode, const SweepArgs<T>& a, int k_local, const T* xin, T* xout,
-                      hipStream_t st);
+hipError_t launch_row(int cfg, int mode, const SweepArgs<T>& a, const SweepArgs<T>* argv,
+                      int nmaps, int k_local, const T* xin, T* xout, hipStream_t st);
 template <class T>
-hipError_t launch_col(int cfg, int mode, const SweepArgs<T>& a, int k_local, void* spec,
-                      double lam_init, hipStream_t st);
+hipError_t launch_col(int cfg, int mode, const SweepArgs<T>& a, const SweepArgs<T>* argv,
+                      int nmaps, int k_local, void* spec, double lam_init, hipStream_t st);
 template <class T>
-hipError_t launch_mon_col(const MonArgs<T>& m, int mode, double lam_out, hipStream_t st);
+hipError_t launch_mon_col(const MonArgs<T>& m, const MonArgs<T>* argv, int nmaps, int mode,
+                          hipStream_t st);
 template <class T>
-hipError_t launch_mon_row(const MonArgs<T>& m, int mode, T* s_out, hipStream_t st);
-hipError_t launch_controller(DevSched* s, double* lam, const double* part, int nblk, double* trace,
-                             hipStream_t st);
+hipError_t launch_mon_row(const MonArgs<T>& m, const MonArgs<T>* argv, int nmaps, int mode,
+                          hipStream_t st);
+hipError_t launch_controller(const CtrlArgs* argv, int nmaps, hipStream_t st);
 template <class T>
 hipError_t launch_stats(const T* d, const T* npix, const uint8_t* mask, const T* sk, const T* poof,
                         const T* pst, int ny, int nx, double* part, int nblk, double* out_pix,

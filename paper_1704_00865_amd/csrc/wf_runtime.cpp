@@ -58,6 +58,12 @@ struct Ctx {
   double* trace = nullptr;
   int trace_cap = 0;
   void* alpha_sk = nullptr;  // flat signal spectrum for the inverse-noise weighting
+  void* d_args = nullptr;    // device argument blocks of the single-map launches
+  void* d_margs = nullptr;
+  void* d_ctrl = nullptr;
+  void* h_args = nullptr;    // pinned staging of the same
+  void* h_margs = nullptr;
+  void* h_ctrl = nullptr;
   DevSched* h_ring = nullptr;  // pinned
   double* h_stats = nullptr;   // pinned
   hipEvent_t ev_ring[kRing] = {};
@@ -77,12 +83,17 @@ wf_status from_hip(hipError_t e) {
     if (e_ != hipSuccess) return from_hip(e_); \
   } while (0)
 
-bool pow2_in(int n, int lo, int hi) { return n >= lo && n <= hi && (n & (n - 1)) == 0; }
+// transform lengths with a built radix plan: powers of two 64..4096 (float64
+// up to 2048) and 3 x 128, 3 x 256, 3 x 512
+bool length_ok(int n, int prec) {
+  if (n == 384 || n == 768 || n == 1536) return true;
+  const int hi = prec == WF_F64 ? 2048 : 4096;
+  return n >= 64 && n <= hi && (n & (n - 1)) == 0;
+}
 
 int supported(int ny, int nx, int prec) {
-  const int hi = prec == WF_F64 ? 2048 : 4096;
   if (prec != WF_F32 && prec != WF_F64) return 0;
-  return pow2_in(ny, 64, hi) && pow2_in(nx, 64, hi);
+  return length_ok(ny, prec) && length_ok(nx, prec);
 }
 
 template <class T>
@@ -98,11 +109,14 @@ void make_table(std::vector<T>& out, int n) {
 void free_ctx(Ctx* c) {
   void* bufs[] = {c->B, c->tA, c->dA, c->tB, c->sc, c->nbA, c->sy, c->sig, c->nbar2, c->twx, c->twy,
                   c->twx_d, c->twy_d, c->Mx, c->My, c->part, c->stats, c->sch, c->lam, c->trace,
-                  c->alpha_sk};
+                  c->alpha_sk, c->d_args, c->d_margs, c->d_ctrl};
   for (void* p : bufs)
     if (p) (void)hipFree(p);
   if (c->h_ring) (void)hipHostFree(c->h_ring);
   if (c->h_stats) (void)hipHostFree(c->h_stats);
+  if (c->h_args) (void)hipHostFree(c->h_args);
+  if (c->h_margs) (void)hipHostFree(c->h_margs);
+  if (c->h_ctrl) (void)hipHostFree(c->h_ctrl);
   for (auto& e : c->ev_ring)
     if (e) (void)hipEventDestroy(e);
   for (auto& e : c->prof_ev)
@@ -156,9 +170,15 @@ wf_status create(const wf_shape* sh, Ctx** out) {
   A(c->part, npart * sizeof(double));
   A(c->stats, 16 * sizeof(double));
   A(c->sch, sizeof(DevSched));
+  A(c->d_args, sizeof(SweepArgs<double>));
+  A(c->d_margs, sizeof(MonArgs<double>));
+  A(c->d_ctrl, sizeof(CtrlArgs));
 #undef A
   hipError_t e = hipHostMalloc((void**)&c->h_ring, kRing * sizeof(DevSched), hipHostMallocDefault);
   if (e == hipSuccess) e = hipHostMalloc((void**)&c->h_stats, 16 * sizeof(double), hipHostMallocDefault);
+  if (e == hipSuccess) e = hipHostMalloc(&c->h_args, sizeof(SweepArgs<double>), hipHostMallocDefault);
+  if (e == hipSuccess) e = hipHostMalloc(&c->h_margs, sizeof(MonArgs<double>), hipHostMallocDefault);
+  if (e == hipSuccess) e = hipHostMalloc(&c->h_ctrl, sizeof(CtrlArgs), hipHostMallocDefault);
   for (int i = 0; i < kRing && e == hipSuccess; ++i)
     e = hipEventCreateWithFlags(&c->ev_ring[i], hipEventDisableTiming);
   if (e != hipSuccess) {
@@ -337,35 +357,59 @@ wf_status check_schedule(const wf_schedule* s) {
   return WF_OK;
 }
 
+// Per-map state of one solve: the chain plan, host copies of the kernel
+// argument blocks, the schedule, and where its device schedule lives.
 template <class T>
-wf_status solve_t(Ctx* c, const wf_inputs* in, const wf_schedule* s, const void* s_init,
-                  void* s_out, wf_report* rep, double* trace, hipStream_t st) {
+struct MapRun {
+  Ctx* c = nullptr;
+  const wf_inputs* in = nullptr;
+  Chain ch;
+  double pix[8] = {0}, spec[8] = {0};
+  SweepArgs<T> a{};
+  MonArgs<T> m{};
+  CtrlArgs ctrl{};
+  DevSched h{};
+  std::vector<double> lam;
+  int n_chunks = 0;
+};
+
+// a group of maps of one shape and chain kind: one launch per kernel
+template <class T>
+struct ShapeClass {
+  std::vector<int> maps;
+  SweepArgs<T>* argv = nullptr;  // device arrays, one entry per map
+  MonArgs<T>* margv = nullptr;
+  int tile = kTileDefault;
+};
+
+// Validation, tau_i, coefficients, schedule and zero/warm start of one map.
+// dsched: where this map's device schedule lives.
+template <class T>
+wf_status map_setup(Ctx* c, const wf_inputs* in, const wf_schedule* s, const void* s_init,
+                    void* s_out, DevSched* dsched, MapRun<T>& r, hipStream_t st) {
+  r.c = c;
+  r.in = in;
   const bool has_oof = in->p_oof != nullptr, has_st = in->p_stripe != nullptr;
-  // 1. validation statistics (one readback)
   WF_TRY(launch_stats<T>((const T*)in->d, (const T*)in->n_pix, in->mask, (const T*)in->s_k,
                          (const T*)in->p_oof, (const T*)in->p_stripe, c->ny, c->nx, c->part,
                          kStatBlocks, c->stats, c->stats + 8, st));
   WF_TRY(hipMemcpyAsync(c->h_stats, c->stats, 16 * sizeof(double), hipMemcpyDeviceToHost, st));
   WF_TRY(hipStreamSynchronize(st));
-  double pix[8], spec[8];
-  std::memcpy(pix, c->h_stats, sizeof(pix));
-  std::memcpy(spec, c->h_stats + 8, sizeof(spec));
-  if (pix[0] < 1) return WF_EINVAL;                       // no observed pixel
-  if (pix[4] > 0) return WF_ENONFINITE;                   // NaN/Inf on observed pixels
-  if (spec[3] > 0 || spec[4] > 0 || spec[5] > 0) return WF_EINVAL;  // bad spectra
-  if (pix[5] > 0) return WF_ENOTPD;                       // N_pix <= 0 observed
-  Chain ch;
-  wf_status ps = plan_chain(c, s, has_oof, has_st, pix, spec, &ch);
+  std::memcpy(r.pix, c->h_stats, sizeof(r.pix));
+  std::memcpy(r.spec, c->h_stats + 8, sizeof(r.spec));
+  if (r.pix[0] < 1) return WF_EINVAL;                             // no observed pixel
+  if (r.pix[4] > 0) return WF_ENONFINITE;                         // NaN/Inf on observed pixels
+  if (r.spec[3] > 0 || r.spec[4] > 0 || r.spec[5] > 0) return WF_EINVAL;  // bad spectra
+  if (r.pix[5] > 0) return WF_ENOTPD;                             // N_pix <= 0 observed
+  wf_status ps = plan_chain(c, s, has_oof, has_st, r.pix, r.spec, &r.ch);
   if (ps != WF_OK) return ps;
-
-  // 2. coefficients
-  WF_TRY(launch_prep<T>((const T*)in->n_pix, in->mask, c->ny, c->nx, ch.phi + ch.tauW, (T*)c->nbar2,
-                        (const T*)in->s_k, (const T*)in->p_oof, (const T*)in->p_stripe, ch.pa,
-                        (T*)c->sc, (T*)c->nbA, (T*)c->sy, (T*)c->sig, st));
-
-  // 3. schedule on the device
+  WF_TRY(launch_prep<T>((const T*)in->n_pix, in->mask, c->ny, c->nx, r.ch.phi + r.ch.tauW,
+                        (T*)c->nbar2, (const T*)in->s_k, (const T*)in->p_oof,
+                        (const T*)in->p_stripe, r.ch.pa, (T*)c->sc, (T*)c->nbA, (T*)c->sy,
+                        (T*)c->sig, st));
+  // schedule: lambda per sweep and the device-side controller state
   const int K = s->monitor_every, maxs = s->max_sweeps;
-  const int n_chunks = (maxs + K - 1) / K;
+  r.n_chunks = (maxs + K - 1) / K;
   if (c->lam_cap < maxs + 1) {
     if (c->lam) (void)hipFree(c->lam);
     c->lam = nullptr;
@@ -374,53 +418,125 @@ wf_status solve_t(Ctx* c, const wf_inputs* in, const wf_schedule* s, const void*
     if (as != WF_OK) return as;
     c->lam_cap = maxs + 1;
   }
-  if (c->trace_cap < n_chunks) {
+  if (c->trace_cap < r.n_chunks) {
     if (c->trace) (void)hipFree(c->trace);
     c->trace = nullptr;
     c->trace_cap = 0;
-    wf_status as = alloc((void**)&c->trace, (size_t)n_chunks * 5 * sizeof(double));
+    wf_status as = alloc((void**)&c->trace, (size_t)r.n_chunks * 5 * sizeof(double));
     if (as != WF_OK) return as;
-    c->trace_cap = n_chunks;
+    c->trace_cap = r.n_chunks;
   }
-  std::vector<double> lam(maxs + 1);
-  for (int k = 0; k <= maxs; ++k) {
-    if (s->kind == WF_SCHED_FIXED) lam[k] = s->lambda[std::min(k, s->n_lambda - 1)];
-    else lam[k] = s->lambda0;
-  }
-  DevSched h{};
-  h.base = 0;
-  h.done = 0;
+  r.lam.assign(maxs + 1, 0.0);
+  for (int k = 0; k <= maxs; ++k)
+    r.lam[k] = s->kind == WF_SCHED_FIXED ? s->lambda[std::min(k, s->n_lambda - 1)] : s->lambda0;
+  DevSched& h = r.h;
+  h = DevSched{};
   h.status = WF_NOT_CONVERGED;
   h.max_sweeps = maxs;
   h.K = K;
   h.adaptive = s->kind == WF_SCHED_ADAPTIVE;
-  h.max_rec = n_chunks;
+  h.max_rec = r.n_chunks;
   h.stop_full = s->stop_full ? 1 : 0;
   h.shrink = s->shrink_exp;
   h.plateau = s->plateau_rtol;
   h.snap = s->snap_eps;
   h.rtol = s->rtol;
-  h.d2 = pix[3];
-  h.nu = pix[2];
-  WF_TRY(hipMemcpyAsync(c->lam, lam.data(), lam.size() * sizeof(double), hipMemcpyHostToDevice, st));
-  WF_TRY(hipMemcpyAsync(c->sch, &h, sizeof(h), hipMemcpyHostToDevice, st));
-
-  SweepArgs<T> a = sweep_args<T>(c, in, ch);
-  MonArgs<T> m = mon_args<T>(c, in, ch);
-
-  // 4. initial state
+  h.d2 = r.pix[3];
+  h.nu = r.pix[2];
+  h.lam_last = r.lam[0];
+  WF_TRY(hipMemcpyAsync(c->lam, r.lam.data(), r.lam.size() * sizeof(double),
+                        hipMemcpyHostToDevice, st));
+  WF_TRY(hipMemcpyAsync(dsched, &h, sizeof(h), hipMemcpyHostToDevice, st));
+  r.a = sweep_args<T>(c, in, r.ch);
+  r.a.sch = dsched;
+  r.m = mon_args<T>(c, in, r.ch);
+  r.m.sch = dsched;
+  r.m.s_out = s_out;
+  r.ctrl = CtrlArgs{dsched, c->lam, c->part, c->ny / kTRM, c->trace};
+  // initial state (the single-map argument block is used for the warm start)
   const size_t modes_b = (size_t)c->nh * c->ny * 2 * c->esz;
   if (s_init) {
-    WF_TRY(launch_row<T>(c->tile, ROW_R2C, a, 0, (const T*)s_init, nullptr, st));
-    WF_TRY(launch_col<T>(c->tile, COL_INIT, a, 0, nullptr, lam[0], st));
+    std::memcpy(c->h_args, &r.a, sizeof(r.a));
+    WF_TRY(hipMemcpyAsync(c->d_args, c->h_args, sizeof(r.a), hipMemcpyHostToDevice, st));
+    WF_TRY(launch_row<T>(c->tile, ROW_R2C, r.a, (const SweepArgs<T>*)c->d_args, 1, 0,
+                         (const T*)s_init, nullptr, st));
+    WF_TRY(launch_col<T>(c->tile, COL_INIT, r.a, (const SweepArgs<T>*)c->d_args, 1, 0, nullptr,
+                         r.lam[0], st));
+    WF_TRY(hipStreamSynchronize(st));
   } else {
     WF_TRY(hipMemsetAsync(c->B, 0, (size_t)c->ny * (c->nx / 2) * 2 * c->esz, st));
     WF_TRY(hipMemsetAsync(c->tA, 0, modes_b, st));
     WF_TRY(hipMemsetAsync(c->dA, 0, modes_b, st));
     WF_TRY(hipMemsetAsync(c->tB, 0, modes_b, st));
   }
+  return WF_OK;
+}
 
-  // 5. sweeps
+// One chunk: K sweeps of every class, then the monitor of every class and
+// the controller of every map.  ev (optional): 5 timing events around the
+// first sweep's row and column launches of class 0 and around the monitor.
+template <class T>
+wf_status enqueue_chunk(std::vector<ShapeClass<T>>& cls, const std::vector<MapRun<T>>& runs,
+                        const CtrlArgs* ctrl_argv, int nmaps, int K, hipEvent_t* ev,
+                        hipStream_t st) {
+  for (int k = 0; k < K; ++k) {
+    for (size_t i = 0; i < cls.size(); ++i) {
+      const SweepArgs<T>& a0 = runs[cls[i].maps[0]].a;
+      const int n = (int)cls[i].maps.size();
+      if (ev && k == 0 && i == 0) WF_TRY(hipEventRecord(ev[0], st));
+      WF_TRY(launch_row<T>(cls[i].tile, ROW_SWEEP, a0, cls[i].argv, n, k, nullptr, nullptr, st));
+      if (ev && k == 0 && i == 0) WF_TRY(hipEventRecord(ev[1], st));
+      WF_TRY(launch_col<T>(cls[i].tile, COL_SWEEP, a0, cls[i].argv, n, k, nullptr, 0.0, st));
+      if (ev && k == 0 && i == 0) WF_TRY(hipEventRecord(ev[2], st));
+    }
+  }
+  if (ev) WF_TRY(hipEventRecord(ev[3], st));
+  for (auto& cl : cls) {
+    const MonArgs<T>& m0 = runs[cl.maps[0]].m;
+    WF_TRY(launch_mon_col<T>(m0, cl.margv, (int)cl.maps.size(), MON_RESIDUAL, st));
+    WF_TRY(launch_mon_row<T>(m0, cl.margv, (int)cl.maps.size(), MON_RESIDUAL, st));
+  }
+  WF_TRY(launch_controller(ctrl_argv, nmaps, st));
+  if (ev) WF_TRY(hipEventRecord(ev[4], st));
+  return WF_OK;
+}
+
+void fill_report(wf_report* rep, const DevSched& fin, const Chain& ch, const double* pix) {
+  std::memset(rep, 0, sizeof(*rep));
+  rep->status = fin.status;
+  rep->sweeps = fin.sweeps_done;
+  rep->n_records = fin.n_rec;
+  rep->n_levels = ch.n_levels;
+  rep->lambda = fin.lam_last;
+  rep->rho = fin.rho;
+  rep->rho_mask = fin.rho_mask;
+  rep->dd2 = fin.dd2;
+  rep->d2 = pix[3];
+  for (int i = 0; i < 3; ++i) rep->tau[i] = ch.tau_report[i];
+  rep->phi = ch.phi;
+}
+
+template <class T>
+wf_status solve_t(Ctx* c, const wf_inputs* in, const wf_schedule* s, const void* s_init,
+                  void* s_out, wf_report* rep, double* trace, hipStream_t st) {
+  std::vector<MapRun<T>> runs(1);
+  MapRun<T>& r = runs[0];
+  wf_status ss = map_setup<T>(c, in, s, s_init, s_out, c->sch, r, st);
+  if (ss != WF_OK) return ss;
+  // argument blocks for the single-map launches
+  std::memcpy(c->h_args, &r.a, sizeof(r.a));
+  std::memcpy(c->h_margs, &r.m, sizeof(r.m));
+  std::memcpy(c->h_ctrl, &r.ctrl, sizeof(r.ctrl));
+  WF_TRY(hipMemcpyAsync(c->d_args, c->h_args, sizeof(r.a), hipMemcpyHostToDevice, st));
+  WF_TRY(hipMemcpyAsync(c->d_margs, c->h_margs, sizeof(r.m), hipMemcpyHostToDevice, st));
+  WF_TRY(hipMemcpyAsync(c->d_ctrl, c->h_ctrl, sizeof(r.ctrl), hipMemcpyHostToDevice, st));
+  std::vector<ShapeClass<T>> cls(1);
+  cls[0].maps = {0};
+  cls[0].argv = (SweepArgs<T>*)c->d_args;
+  cls[0].margv = (MonArgs<T>*)c->d_margs;
+  cls[0].tile = c->tile;
+
+  const int K = s->monitor_every;
   const bool prof = c->profiling != 0;
   if (prof && (int)c->prof_ev.size() < kProfSlots) {
     for (int i = (int)c->prof_ev.size(); i < kProfSlots; ++i) {
@@ -433,21 +549,10 @@ wf_status solve_t(Ctx* c, const wf_inputs* in, const wf_schedule* s, const void*
   }
   const int prof_chunks = kProfSlots / 5;
   int launched = 0;
-  for (int ci = 0; ci < n_chunks; ++ci) {
-    const bool sample = prof && ci < prof_chunks;
-    hipEvent_t* ev = sample ? &c->prof_ev[5 * ci] : nullptr;
-    for (int k = 0; k < K; ++k) {
-      if (sample && k == 0) WF_TRY(hipEventRecord(ev[0], st));
-      WF_TRY(launch_row<T>(c->tile, ROW_SWEEP, a, k, nullptr, nullptr, st));
-      if (sample && k == 0) WF_TRY(hipEventRecord(ev[1], st));
-      WF_TRY(launch_col<T>(c->tile, COL_SWEEP, a, k, nullptr, 0.0, st));
-      if (sample && k == 0) WF_TRY(hipEventRecord(ev[2], st));
-    }
-    if (sample) WF_TRY(hipEventRecord(ev[3], st));
-    WF_TRY(launch_mon_col<T>(m, MON_RESIDUAL, 0.0, st));
-    WF_TRY(launch_mon_row<T>(m, MON_RESIDUAL, nullptr, st));
-    WF_TRY(launch_controller(c->sch, c->lam, c->part, c->ny / kTRM, c->trace, st));
-    if (sample) WF_TRY(hipEventRecord(ev[4], st));
+  for (int ci = 0; ci < r.n_chunks; ++ci) {
+    hipEvent_t* ev = (prof && ci < prof_chunks) ? &c->prof_ev[5 * ci] : nullptr;
+    wf_status es = enqueue_chunk<T>(cls, runs, (const CtrlArgs*)c->d_ctrl, 1, K, ev, st);
+    if (es != WF_OK) return es;
     const int slot = ci % kRing;
     WF_TRY(hipMemcpyAsync(&c->h_ring[slot], c->sch, sizeof(DevSched), hipMemcpyDeviceToHost, st));
     WF_TRY(hipEventRecord(c->ev_ring[slot], st));
@@ -462,27 +567,16 @@ wf_status solve_t(Ctx* c, const wf_inputs* in, const wf_schedule* s, const void*
   DevSched fin;
   WF_TRY(hipMemcpy(&fin, c->sch, sizeof(fin), hipMemcpyDeviceToHost));
 
-  // 6. output s = S x, x = t_A / (S_chain + T_A) at the last lambda
-  WF_TRY(launch_mon_col<T>(m, MON_OUTPUT, fin.lam_last, st));
-  WF_TRY(launch_mon_row<T>(m, MON_OUTPUT, (T*)s_out, st));
+  // output s = S x, x = t_A / (S_chain + T_A) at the last lambda
+  WF_TRY(launch_mon_col<T>(r.m, cls[0].margv, 1, MON_OUTPUT, st));
+  WF_TRY(launch_mon_row<T>(r.m, cls[0].margv, 1, MON_OUTPUT, st));
   if (trace && fin.n_rec > 0)
     WF_TRY(hipMemcpyAsync(trace, c->trace, (size_t)fin.n_rec * 5 * sizeof(double),
                           hipMemcpyDeviceToHost, st));
   WF_TRY(hipStreamSynchronize(st));
 
   if (rep) {
-    std::memset(rep, 0, sizeof(*rep));
-    rep->status = fin.status;
-    rep->sweeps = fin.sweeps_done;
-    rep->n_records = fin.n_rec;
-    rep->n_levels = ch.n_levels;
-    rep->lambda = fin.lam_last;
-    rep->rho = fin.rho;
-    rep->rho_mask = fin.rho_mask;
-    rep->dd2 = fin.dd2;
-    rep->d2 = pix[3];
-    for (int i = 0; i < 3; ++i) rep->tau[i] = ch.tau_report[i];
-    rep->phi = ch.phi;
+    fill_report(rep, fin, r.ch, r.pix);
     if (prof) {
       const int last_chunk = fin.sweeps_done > 0 ? (fin.sweeps_done - 1) / K : 0;
       const int nsamp = std::min(std::min(launched, prof_chunks), last_chunk + 1);
@@ -504,16 +598,161 @@ wf_status solve_t(Ctx* c, const wf_inputs* in, const wf_schedule* s, const void*
   return (wf_status)fin.status;
 }
 
+// Batched solve: maps of equal shape and chain kind share every launch; a
+// chunk of sweeps is captured once in a HIP graph and replayed.
+template <class T>
+wf_status solve_batch_t(Ctx** ctxs, int n, const wf_inputs* ins, const wf_schedule* s,
+                        void* const* s_out, wf_report* reps, hipStream_t user_st) {
+  std::vector<MapRun<T>> runs(n);
+  // device buffers of this call: schedules, argument blocks, controller args
+  DevSched* dsch = nullptr;
+  SweepArgs<T>* dargs = nullptr;
+  MonArgs<T>* dmargs = nullptr;
+  CtrlArgs* dctrl = nullptr;
+  DevSched* hring = nullptr;
+  hipStream_t cs = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  hipEvent_t ev_in = nullptr, ev_ring[kRing] = {};
+  wf_status ret = WF_OK;
+  auto cleanup = [&]() {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    if (cs) (void)hipStreamDestroy(cs);
+    if (ev_in) (void)hipEventDestroy(ev_in);
+    for (auto& e : ev_ring)
+      if (e) (void)hipEventDestroy(e);
+    if (hring) (void)hipHostFree(hring);
+    if (dsch) (void)hipFree(dsch);
+    if (dargs) (void)hipFree(dargs);
+    if (dmargs) (void)hipFree(dmargs);
+    if (dctrl) (void)hipFree(dctrl);
+  };
+#define BT(expr)                          \
+  do {                                    \
+    hipError_t e_ = (expr);               \
+    if (e_ != hipSuccess) {               \
+      cleanup();                          \
+      return from_hip(e_);                \
+    }                                     \
+  } while (0)
+  BT(hipMalloc((void**)&dsch, (size_t)n * sizeof(DevSched)));
+  BT(hipMalloc((void**)&dargs, (size_t)n * sizeof(SweepArgs<T>)));
+  BT(hipMalloc((void**)&dmargs, (size_t)n * sizeof(MonArgs<T>)));
+  BT(hipMalloc((void**)&dctrl, (size_t)n * sizeof(CtrlArgs)));
+  BT(hipHostMalloc((void**)&hring, (size_t)kRing * n * sizeof(DevSched), hipHostMallocDefault));
+  for (int i = 0; i < n; ++i) {
+    wf_status ms = map_setup<T>(ctxs[i], &ins[i], s, nullptr, s_out[i], dsch + i, runs[i], user_st);
+    if (ms != WF_OK) {
+      (void)hipStreamSynchronize(user_st);
+      cleanup();
+      return ms;
+    }
+  }
+  // classes of (shape, chain kind); argument blocks laid out class by class
+  std::vector<ShapeClass<T>> cls;
+  std::vector<int> order;
+  for (int i = 0; i < n; ++i) {
+    bool placed = false;
+    for (auto& cl : cls) {
+      const MapRun<T>& r0 = runs[cl.maps[0]];
+      if (r0.c->ny == runs[i].c->ny && r0.c->nx == runs[i].c->nx && r0.a.fk == runs[i].a.fk &&
+          r0.c->tile == runs[i].c->tile) {
+        cl.maps.push_back(i);
+        placed = true;
+        break;
+      }
+    }
+    if (!placed) {
+      ShapeClass<T> cl;
+      cl.maps = {i};
+      cl.tile = runs[i].c->tile;
+      cls.push_back(cl);
+    }
+  }
+  std::vector<SweepArgs<T>> ha;
+  std::vector<MonArgs<T>> hm;
+  std::vector<CtrlArgs> hc;
+  for (auto& cl : cls) {
+    cl.argv = dargs + ha.size();
+    cl.margv = dmargs + hm.size();
+    for (int i : cl.maps) {
+      ha.push_back(runs[i].a);
+      hm.push_back(runs[i].m);
+    }
+  }
+  for (int i = 0; i < n; ++i) hc.push_back(runs[i].ctrl);
+  BT(hipMemcpyAsync(dargs, ha.data(), ha.size() * sizeof(SweepArgs<T>), hipMemcpyHostToDevice, user_st));
+  BT(hipMemcpyAsync(dmargs, hm.data(), hm.size() * sizeof(MonArgs<T>), hipMemcpyHostToDevice, user_st));
+  BT(hipMemcpyAsync(dctrl, hc.data(), hc.size() * sizeof(CtrlArgs), hipMemcpyHostToDevice, user_st));
+  // the sweeps run on a stream of this call (a captured stream cannot be the
+  // legacy default stream); it starts after the set-up on the caller's stream
+  BT(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+  BT(hipEventCreateWithFlags(&ev_in, hipEventDisableTiming));
+  for (int i = 0; i < kRing; ++i) BT(hipEventCreateWithFlags(&ev_ring[i], hipEventDisableTiming));
+  BT(hipEventRecord(ev_in, user_st));
+  BT(hipStreamWaitEvent(cs, ev_in, 0));
+  const int K = s->monitor_every;
+  int n_chunks = 0;
+  for (auto& r : runs) n_chunks = std::max(n_chunks, r.n_chunks);
+  BT(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+  wf_status es = enqueue_chunk<T>(cls, runs, dctrl, n, K, nullptr, cs);
+  hipError_t ce = hipStreamEndCapture(cs, &graph);
+  if (es != WF_OK) {
+    cleanup();
+    return es;
+  }
+  BT(ce);
+  BT(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
+  for (int ci = 0; ci < n_chunks; ++ci) {
+    BT(hipGraphLaunch(exec, cs));
+    const int slot = ci % kRing;
+    BT(hipMemcpyAsync(hring + (size_t)slot * n, dsch, (size_t)n * sizeof(DevSched),
+                      hipMemcpyDeviceToHost, cs));
+    BT(hipEventRecord(ev_ring[slot], cs));
+    if (ci >= kLag) {
+      const int chk = (ci - kLag) % kRing;
+      BT(hipEventSynchronize(ev_ring[chk]));
+      bool all = true;
+      for (int i = 0; i < n; ++i) all = all && hring[(size_t)chk * n + i].done;
+      if (all) break;
+    }
+  }
+  BT(hipStreamSynchronize(cs));
+  std::vector<DevSched> fin(n);
+  BT(hipMemcpy(fin.data(), dsch, (size_t)n * sizeof(DevSched), hipMemcpyDeviceToHost));
+  for (auto& cl : cls) {
+    const MonArgs<T>& m0 = runs[cl.maps[0]].m;
+    BT(launch_mon_col<T>(m0, cl.margv, (int)cl.maps.size(), MON_OUTPUT, cs));
+    BT(launch_mon_row<T>(m0, cl.margv, (int)cl.maps.size(), MON_OUTPUT, cs));
+  }
+  BT(hipStreamSynchronize(cs));
+#undef BT
+  int worst = WF_OK;
+  for (int i = 0; i < n; ++i) {
+    if (reps) fill_report(&reps[i], fin[i], runs[i].ch, runs[i].pix);
+    const int sti = fin[i].status;
+    if (sti < 0) worst = std::min(worst, sti);
+    else if (worst >= 0) worst = std::max(worst, sti);
+  }
+  ret = (wf_status)worst;
+  cleanup();
+  return ret;
+}
+
 template <class T>
 wf_status fft_t(Ctx* c, const void* src, void* dst, bool forward, hipStream_t st) {
   Chain ch;
   SweepArgs<T> a = sweep_args<T>(c, nullptr, ch);
+  std::memcpy(c->h_args, &a, sizeof(a));
+  WF_TRY(hipMemcpyAsync(c->d_args, c->h_args, sizeof(a), hipMemcpyHostToDevice, st));
+  const SweepArgs<T>* argv = (const SweepArgs<T>*)c->d_args;
   if (forward) {
-    WF_TRY(launch_row<T>(kTileDefault, ROW_R2C, a, 0, (const T*)src, nullptr, st));
-    WF_TRY(launch_col<T>(kTileDefault, COL_FWD_OUT, a, 0, dst, 0.0, st));
+    WF_TRY(launch_row<T>(kTileDefault, ROW_R2C, a, argv, 1, 0, (const T*)src, nullptr, st));
+    WF_TRY(launch_col<T>(kTileDefault, COL_FWD_OUT, a, argv, 1, 0, dst, 0.0, st));
   } else {
-    WF_TRY(launch_col<T>(kTileDefault, COL_INV_IN, a, 0, const_cast<void*>(src), 0.0, st));
-    WF_TRY(launch_row<T>(kTileDefault, ROW_C2R, a, 0, nullptr, (T*)dst, st));
+    WF_TRY(launch_col<T>(kTileDefault, COL_INV_IN, a, argv, 1, 0, const_cast<void*>(src), 0.0, st));
+    WF_TRY(launch_row<T>(kTileDefault, ROW_C2R, a, argv, 1, 0, nullptr, (T*)dst, st));
   }
   WF_TRY(hipStreamSynchronize(st));
   return WF_OK;
@@ -567,6 +806,28 @@ wf_status wf_solve(void* ctx, const wf_inputs* in, const wf_schedule* sch, const
   if (hipGetDevice(&dev) != hipSuccess || dev != c->device) return WF_EINVAL;
   if (c->prec == WF_F64) return solve_t<double>(c, in, sch, s_init, s_out, rep, trace, stream);
   return solve_t<float>(c, in, sch, s_init, s_out, rep, trace, stream);
+}
+
+wf_status wf_solve_batch(void* const* ctxs, int32_t n, const wf_inputs* inputs,
+                         const wf_schedule* sch, void* const* s_out, wf_report* reps,
+                         hipStream_t stream) {
+  if (!ctxs || !inputs || !sch || !s_out || n < 1 || n > WF_BATCH_MAX) return WF_EINVAL;
+  wf_status v = check_schedule(sch);
+  if (v != WF_OK) return v;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return WF_EDEVICE;
+  std::vector<Ctx*> cs(n);
+  for (int i = 0; i < n; ++i) {
+    Ctx* c = (Ctx*)ctxs[i];
+    const wf_inputs& in = inputs[i];
+    if (!c || !s_out[i] || !in.d || !in.s_k || !in.n_pix) return WF_EINVAL;
+    if (c->device != dev || c->prec != ((Ctx*)ctxs[0])->prec) return WF_EINVAL;
+    for (int j = 0; j < i; ++j)
+      if (cs[j] == c) return WF_EINVAL;  // each map needs its own context
+    cs[i] = c;
+  }
+  if (cs[0]->prec == WF_F64) return solve_batch_t<double>(cs.data(), n, inputs, sch, s_out, reps, stream);
+  return solve_batch_t<float>(cs.data(), n, inputs, sch, s_out, reps, stream);
 }
 
 wf_status wf_inverse_noise_weight(void* ctx, const wf_inputs* in, double alpha,

@@ -84,6 +84,16 @@ def test_iterate_parity_masked_nonsquare(gpu_lib, prec, shape):
 
 
 @pytest.mark.parametrize("prec", ["f64", "f32"])
+@pytest.mark.parametrize("shape", [(384, 128), (128, 768), (768, 384), (1536, 64)])
+def test_iterate_parity_radix3_lengths(gpu_lib, prec, shape):
+    """Lengths 3 x 2^k use a radix-3 pass (384, 768, 1536)."""
+    ny, nx = shape
+    p = synth.make_problem(ny, nx, 23, mask_frac=0.05)
+    s_gpu, rep, trace, res = _run_both(gpu_lib, p, prec, _ramp(10, 20), monitor_every=8)
+    assert _rel(s_gpu, res.s) < TOL[prec]
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
 @pytest.mark.parametrize("terms", [("oof",), ("stripe",), (), ("oof", "stripe")])
 @pytest.mark.parametrize("chain", ["three", "merged", "augmented"])
 def test_iterate_parity_term_subsets(gpu_lib, prec, terms, chain):
