@@ -24,12 +24,18 @@ Contents and what pins each part (tests marked ``not gpu``):
                 (1-pixel algebra, white-noise-only Fourier closed form).
 * ``variants``  the two-level merged chain and the augmented-signal chain
                 (Appendix A shortcuts); pinned by sharing the fixed point.
+* ``warmnet``   the convolutional warm-start predictor (not from the paper:
+                the iteration may start anywhere, Section 2): circular 3x3
+                convolutions, pooling, upsampling, forward and reverse-mode
+                gradient, Adam.  Pinned by brute-force loops, adjoint
+                identities, translation equivariance and central finite
+                differences of the loss.
 
 Parity unpinned: the adaptive-schedule trajectory (lambda decisions depend on
 rounding); tests replay a recorded lambda sequence as a fixed schedule instead.
 """
 
-from . import bases, direct, messenger  # noqa: F401
+from . import bases, direct, messenger, warmnet  # noqa: F401
 from .messenger import (  # noqa: F401
     AdaptiveSchedule,
     FixedSchedule,

@@ -17,7 +17,7 @@ INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libwf.so")
 BUILD_DIR = os.path.join(PKG, "_build")
 
-SOURCES = ["wf_kernels.hip", "wf_runtime.cpp"]
+SOURCES = ["wf_kernels.hip", "wf_runtime.cpp", "wf_nn.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950",

@@ -220,3 +220,20 @@ def named_config(name: str) -> Problem:
     if name == "c3_small":
         return make_problem(256, 256, 3, mask_frac=0.10)
     raise KeyError(name)
+
+
+def survey_batch(sizes=(256, 768, 1536), per_size: int = 16, base_seed: int = 4000):
+    """Batch of independent maps of uneven size (default 16 each of 256^2,
+    768^2 and 1536^2, 48 maps, 48.2 M pixels).  Map i (in order of the sizes)
+    uses seed base_seed + i and a noise level L_i drawn uniformly in
+    [5, 30] uK-arcmin from its own generator: the 1/f floor is L_i and the
+    white level is L_i per 2' pixel (sigma_0 = L_i / 2 uK).  No mask."""
+    out = []
+    i = 0
+    for n in sizes:
+        for _ in range(per_size):
+            seed = base_seed + i
+            lvl = float(np.random.default_rng([seed, 77]).uniform(5.0, 30.0))
+            out.append(make_problem(n, n, seed, oof_level=lvl, white_sigma=lvl / 2.0))
+            i += 1
+    return out

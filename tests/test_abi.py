@@ -1,5 +1,5 @@
-"""The C-ABI library loads and exports what include/wf.h declares (CPU only:
-no compute call is made)."""
+"""The C-ABI library loads and exports what include/wf.h and include/wf_nn.h
+declare (CPU only: no compute call is made)."""
 
 import ctypes
 import os
@@ -11,11 +11,12 @@ import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 HEADER = os.path.join(ROOT, "include", "wf.h")
+NN_HEADER = os.path.join(ROOT, "include", "wf_nn.h")
 LIB = os.path.join(ROOT, "paper_1704_00865_amd", "libwf.so")
 
 
-def _declared():
-    text = open(HEADER).read()
+def _declared(header=HEADER):
+    text = open(header).read()
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
     return sorted(set(re.findall(r"\b(wf_[a-z0-9_]+)\s*\(", text)))
 
@@ -29,15 +30,18 @@ def test_header_declares_the_boundary():
 @pytest.mark.skipif(not os.path.exists(LIB), reason="libwf.so not built")
 def test_library_exports_every_declared_symbol():
     lib = ctypes.CDLL(LIB)
-    missing = [n for n in _declared() if not hasattr(lib, n)]
+    missing = [n for n in _declared() + _declared(NN_HEADER) if not hasattr(lib, n)]
     assert not missing, missing
 
 
 @pytest.mark.skipif(not os.path.exists(LIB), reason="libwf.so not built")
 def test_binding_declares_every_export():
     import paper_1704_00865_amd as wf
+    import paper_1704_00865_amd.nn as nn
     assert sorted(wf.EXPORTS) == _declared()
+    assert sorted(nn.EXPORTS) == _declared(NN_HEADER)
     wf.load()
+    nn._lib()
 
 
 @pytest.mark.skipif(not os.path.exists(LIB), reason="libwf.so not built")
@@ -55,20 +59,28 @@ def test_host_only_calls():
     assert list(s.beta) == [0.9, 0.9, 1.0] and s.chain == 0
     for code in (0, 1, -1, -2, -3, -4, -5, -6):
         assert wf.strerror(code)
+    import paper_1704_00865_amd.nn as nn
+    offs = nn.layer_offsets()
+    assert len(offs) == 15
+    assert nn.param_count() == offs[-1][3] + offs[-1][1]
+    assert offs[0][:2] == (32, 32) and offs[-1][:2] == (32, 32)
 
 
 @pytest.mark.skipif(shutil.which("gcc") is None, reason="no gcc")
 def test_ctypes_layout_matches_c_structs(tmp_path):
     import paper_1704_00865_amd as wf
     src = tmp_path / "sz.c"
-    src.write_text('#include <stdio.h>\n#include <stddef.h>\n#include "wf.h"\n'
-                   "int main(void){printf(\"%zu %zu %zu %zu %zu %zu\\n\", sizeof(wf_schedule),"
+    src.write_text('#include <stdio.h>\n#include <stddef.h>\n#include "wf_nn.h"\n'
+                   "int main(void){printf(\"%zu %zu %zu %zu %zu %zu %zu\\n\", sizeof(wf_schedule),"
                    " sizeof(wf_report), sizeof(wf_inputs), sizeof(wf_shape),"
-                   " offsetof(wf_schedule, chain), offsetof(wf_report, kernel_ms));return 0;}\n")
+                   " offsetof(wf_schedule, chain), offsetof(wf_report, kernel_ms),"
+                   " sizeof(wf_nn_shape));return 0;}\n")
     exe = tmp_path / "sz"
     subprocess.check_call(["gcc", "-D__HIP_PLATFORM_AMD__", "-I", os.path.join(ROOT, "include"),
                            "-I", "/opt/rocm/include", str(src), "-o", str(exe)])
+    import paper_1704_00865_amd.nn as nn
     got = [int(v) for v in subprocess.check_output([str(exe)]).split()]
     assert got == [ctypes.sizeof(wf._Schedule), ctypes.sizeof(wf._Report),
                    ctypes.sizeof(wf._Inputs), ctypes.sizeof(wf._Shape),
-                   wf._Schedule.chain.offset, wf._Report.kernel_ms.offset]
+                   wf._Schedule.chain.offset, wf._Report.kernel_ms.offset,
+                   ctypes.sizeof(nn._NNShape)]
