@@ -15,6 +15,12 @@ Also printed, on the same JSON line:
   time_to_rtol  wall time of a zero-start solve to rho <= 1e-6 on the float64
                 path with the augmented chain (float32 fields settle at a few
                 1e-5 on this map; the three-level chain needs far more sweeps)
+  batch         48 maps of three sizes (16 each of 256^2, 768^2, 1536^2) in
+                one batched solve (shared launches, replayed HIP graph), against
+                the same maps solved one after the other
+  warm_start    the learned warm start: a network trained in the run on solver
+                solutions of 256^2 maps, then sweeps to rho <= 1e-6 on held-out
+                maps from the zero start and from the network's prediction
   cpu_baseline  the float64 CPU oracle on a bounded sample of sweeps
 """
 
@@ -78,6 +84,11 @@ def _args():
     ap.add_argument("--skip-cpu", action="store_true")
     ap.add_argument("--skip-ttr", action="store_true")
     ap.add_argument("--skip-batch", action="store_true")
+    ap.add_argument("--skip-warm", action="store_true")
+    ap.add_argument("--warm-size", type=int, default=256)
+    ap.add_argument("--warm-train", type=int, default=512)
+    ap.add_argument("--warm-test", type=int, default=16)
+    ap.add_argument("--warm-epochs", type=int, default=30)
     ap.add_argument("--batch-steps", type=int, default=2)
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain 1 GiB device copy (counter calibration)")
@@ -291,6 +302,20 @@ def main():
     if not a.skip_batch:
         batch = bench_batch(wf, oracle, synth, torch, dev, a)
 
+    warm = None
+    if not a.skip_warm:
+        from paper_1704_00865_amd import warmstart
+        n_w = a.warm_size
+        print(f"[bench] warm start: generating {a.warm_train}+{a.warm_test} maps of {n_w}^2",
+              file=sys.stderr, flush=True)
+        trp = [synth.make_problem(n_w, n_w, 10000 + i, mask_frac=0.10) for i in range(a.warm_train)]
+        tep = [synth.make_problem(n_w, n_w, 20000 + i, mask_frac=0.10) for i in range(a.warm_test)]
+        warm = warmstart.experiment(trp, tep, epochs=a.warm_epochs, batch=16, lr=2e-3,
+                                    log=lambda m: print(f"[bench] {m}", file=sys.stderr, flush=True))
+        warm["recipe"] = (f"{n_w}^2 maps, three noise terms, 10% disc mask; train seeds "
+                          f"10000-{10000 + a.warm_train - 1}, test seeds 20000-{20000 + a.warm_test - 1}; "
+                          "targets and evaluation: float64 augmented chain, field_mode 1")
+
     cpu = None
     if not a.skip_cpu:
         cores = min(16, os.cpu_count() or 1)
@@ -334,6 +359,7 @@ def main():
         "roofline": roof,
         "time_to_rtol": ttr,
         "batch": batch,
+        "warm_start": warm,
         "cpu_baseline": cpu,
         "final_rho": rep["rho"] if rep else None,
     }

@@ -101,6 +101,14 @@ typedef struct {         /* HOST struct */
   double floor_frac;     /* alpha: white floor lent to the stripe level                 */
   int32_t chain;         /* wf_chain                                                    */
   int32_t stop_full;     /* 1: stop test uses hypot(rho, rho_mask) instead of rho       */
+  int32_t field_mode;    /* 0: s_init and s_out are the signal s.  1: both are the      */
+                         /*   chain's signal-end field u = S_chain x, x = S^-1 s: u = s */
+                         /*   for the three-level and merged chains, u = s + N_F x for  */
+                         /*   the augmented one (its messenger's signal side, App. A).  */
+                         /*   A warm start then hands s_init unsmoothed to the white    */
+                         /*   level when the chain has no Fourier-diagonal messenger    */
+                         /*   (augmented, or white noise only); with one, the signal    */
+                         /*   end is recomputed from t_0 each sweep and modes agree     */
 } wf_schedule;
 
 typedef struct {         /* HOST struct filled by wf_solve */
@@ -151,16 +159,18 @@ wf_status wf_solve(void* ctx, const wf_inputs* in, const wf_schedule* sch,
  *              per map (the context fixes the map's shape and tiling);
  *   inputs[n]  HOST array of per-map inputs (DEVICE pointers inside);
  *   sch        one schedule for every map (adaptive or fixed);
+ *   s_init[n]  HOST array of DEVICE warm starts [ny_i*nx_i] (as for
+ *              wf_solve; an entry may be NULL), or NULL for zero starts;
  *   s_out[n]   HOST array of DEVICE output pointers [ny_i*nx_i];
  *   reps[n]    HOST reports, or NULL.
- * Zero start only.  Returns the most severe error of any map, else
+ * Returns the most severe error of any map, else
  * WF_NOT_CONVERGED if any map ran out of sweeps, else WF_OK; per-map status
  * is in reps[i].status.  Input errors are found before any sweep runs.
  * Allocates its per-call device buffers and graph and frees them before it
  * returns; synchronises stream. */
 wf_status wf_solve_batch(void* const* ctxs, int32_t n, const wf_inputs* inputs,
-                         const wf_schedule* sch, void* const* s_out, wf_report* reps,
-                         hipStream_t stream);
+                         const wf_schedule* sch, const void* const* s_init, void* const* s_out,
+                         wf_report* reps, hipStream_t stream);
 
 /* Approximate inverse-noise weighting N^-1 d (Section 4): the Wiener filter
  * with a small flat signal covariance S = alpha I gives
@@ -168,8 +178,8 @@ wf_status wf_solve_batch(void* const* ctxs, int32_t n, const wf_inputs* inputs,
  * order alpha / (smallest eigenvalue of N).  in->s_k is ignored; masked
  * pixels come out as 0 (their inverse variance).  s_init, if given, is a
  * warm start of the signal-side field alpha (alpha + N)^-1 d.  Other
- * arguments, outputs and errors as for wf_solve; out receives the weighted
- * map. */
+ * arguments, outputs and errors as for wf_solve (sch->field_mode must be 0);
+ * out receives the weighted map. */
 wf_status wf_inverse_noise_weight(void* ctx, const wf_inputs* in, double alpha,
                                   const wf_schedule* sch, const void* s_init, void* out,
                                   wf_report* rep, double* trace, hipStream_t stream);

@@ -12,14 +12,16 @@
  *   convolution + ReLU stages per encoder level; per decoder level a nearest
  *   upsampling, a convolution + ReLU to C_l channels, the encoder skip added,
  *   and a second convolution + ReLU; a final convolution to one channel.
- * Inputs (three channels): d / sigma, log(N_pix / sigma^2) on observed
- * pixels (0 on masked ones) and the mask, sigma^2 = mean N_pix over observed
- * pixels of that map.  Output: s / sigma.
+ * Inputs (four channels): d / sigma, log(N_pix / sigma^2) on observed
+ * pixels (0 on masked ones), the mask, and the mean of d / sigma over the
+ * observed pixels of the pixel's row (row-constant stripe noise spans whole
+ * rows), with sigma^2 = mean N_pix over observed pixels of that map.
+ * Output: the predicted field / sigma.
  *
  * Parameters: one float32 vector.  Convolution i in network order holds
  * W_i [3][3][ci_i][co_i] (row-major, the tap (dy+1, dx+1) first, then the
  * input channel, then the output channel) followed by b_i [co_i], with
- * ci_0 = 32 (three real input channels, the rest must be zero) and
+ * ci_0 = 32 (four real input channels, the rest must be zero) and
  * co_14 = 32 (one real output channel, the rest must be zero).  The
  * convolution is a cross-correlation on the torus:
  *   out[y][x][co] = b[co] + sum_{dy,dx,ci} in[(y+dy)%H][(x+dx)%W][ci] W[dy+1][dx+1][ci][co].
@@ -73,7 +75,7 @@ wf_status wf_nn_train_step(void* net, int32_t n, const void* d, const void* n_pi
                            const uint8_t* mask, const void* s_target, float lr,
                            double* loss, hipStream_t stream);
 
-/* Network alone, on given features: x [n][H][W][3] float32 (DEVICE).
+/* Network alone, on given features: x [n][H][W][4] float32 (DEVICE).
  * y [n][H][W] float32 (DEVICE) receives the output channel. */
 wf_status wf_nn_forward_features(void* net, int32_t n, const float* x, float* y,
                                  hipStream_t stream);

@@ -73,6 +73,12 @@ def observed_index(problem) -> np.ndarray:
 def wiener_dense(problem, refine: int = 2) -> np.ndarray:
     """s = S P^T (P (S+N) P^T)^-1 P d by Cholesky, with a few steps of
     iterative refinement (residual in extended precision)."""
+    S, _ = dense_covariances(problem)
+    return (S @ wiener_dense_x(problem, refine).ravel()).reshape(problem.d.shape)
+
+
+def wiener_dense_x(problem, refine: int = 2) -> np.ndarray:
+    """x = S^-1 s = P^T (P (S+N) P^T)^-1 P d (zero on masked pixels)."""
     S, N = dense_covariances(problem)
     P = observed_index(problem)
     A = (S + N)[np.ix_(P, P)]
@@ -84,8 +90,9 @@ def wiener_dense(problem, refine: int = 2) -> np.ndarray:
     for _ in range(refine):
         r = (bl - Al @ z.astype(np.longdouble)).astype(np.float64)
         z = z + sla.cho_solve(cf, r)
-    s = S[:, P] @ z
-    return s.reshape(problem.d.shape)
+    x = np.zeros(problem.d.size)
+    x[P] = z
+    return x.reshape(problem.d.shape)
 
 
 def chi2_dense(problem, s: np.ndarray) -> float:

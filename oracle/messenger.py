@@ -178,8 +178,15 @@ class State:
     s: np.ndarray
 
 
-def init_state(st: Setup, lam0: float, s_init: Optional[np.ndarray] = None) -> State:
-    """Zero start s = t = d = 0 (Section 2), or every field set to s_init."""
+def init_state(st: Setup, lam0: float, s_init: Optional[np.ndarray] = None,
+               chain_field: bool = False) -> State:
+    """Zero start s = t = d = 0 (Section 2), or every field set to s_init.
+
+    The field at the signal end of the chain is then S_c (S_c + lam0 tau_0)^-1
+    s_init (one signal update of the messenger s_init), or s_init itself when
+    ``chain_field`` says that s_init already is that field and the chain has
+    no Fourier-diagonal messenger level (a chain with one recomputes its
+    signal end from t_0 in every sweep, so both readings start alike)."""
     m = len(st.levels)
     if s_init is None:
         z = np.zeros(st.shape)
@@ -187,7 +194,10 @@ def init_state(st: Setup, lam0: float, s_init: Optional[np.ndarray] = None) -> S
                      dd=[z.copy() for _ in range(m - 1)], s=z.copy())
     u = np.asarray(s_init, dtype=np.float64)
     T0 = lam0 * st.levels[0].tau
-    s = st.S_chain.apply_fn(lambda e: e / (e + T0), u)
+    if chain_field and len(st.levels) == 1:
+        s = u.copy()
+    else:
+        s = st.S_chain.apply_fn(lambda e: e / (e + T0), u)
     return State(t=[u.copy() for _ in range(m)],
                  dd=[u.copy() for _ in range(m - 1)], s=s)
 
@@ -325,18 +335,21 @@ class Result:
 def solve(problem, schedule, *, settings: Settings = Settings(),
           s_init: Optional[np.ndarray] = None, max_sweeps: int = 1000,
           monitor_every: int = 1, rtol: float = 0.0,
-          full_residual: bool = False) -> Result:
+          full_residual: bool = False, chain_field: bool = False) -> Result:
     """Iterate sweeps under a cooling schedule.
 
     Every ``monitor_every`` sweeps (and after the last sweep) the residual is
     evaluated; the solve stops when lam = 1 and rho <= rtol, or after
     ``max_sweeps`` (with ``full_residual`` the test uses hypot(rho, rho_mask)).
+    With ``chain_field`` the warm start and the result are the chain's
+    signal-end field u = S_chain x instead of s = S x (they differ only for
+    the augmented chain, where u = s + N_F x).
     An adaptive schedule changes lam only at those points:
     if |dd2 - dd2_prev| < plateau * (sweeps since prev) * dd2, lam <- lam^shrink.
     """
     st = setup(problem, settings)
     lam = schedule.first()
-    x = init_state(st, lam, s_init)
+    x = init_state(st, lam, s_init, chain_field)
     res = Result(s=x.s, sweeps=0, converged=False)
     prev = None  # (k, dd2)
     adaptive = isinstance(schedule, AdaptiveSchedule)
@@ -362,7 +375,7 @@ def solve(problem, schedule, *, settings: Settings = Settings(),
                     if lam - 1.0 < schedule.snap:
                         lam = 1.0
                 prev = (k - 1, dg.dd2)
-    res.s = final_signal(st, x, lam)
+    res.s = final_chain_field(st, x, lam) if chain_field else final_signal(st, x, lam)
     res.sweeps = k
     res.state = x
     return res
@@ -373,6 +386,13 @@ def final_signal(st: Setup, x: State, lam: float) -> np.ndarray:
     merged chains, followed by s = S S'^-1 u for the augmented chain."""
     T0 = lam * st.levels[0].tau
     return st.S.apply(st.S_chain.apply_fn(lambda e: 1.0 / (e + T0), x.t[0]))
+
+
+def final_chain_field(st: Setup, x: State, lam: float) -> np.ndarray:
+    """u = S_chain (S_chain + T_0)^-1 t_0: the field at the signal end of the
+    chain (equal to s except for the augmented chain)."""
+    T0 = lam * st.levels[0].tau
+    return st.S_chain.apply_fn(lambda e: e / (e + T0), x.t[0])
 
 
 def rfft2_of(u):

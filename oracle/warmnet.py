@@ -20,10 +20,12 @@ level by 2x2 averaging, nearest-neighbour upsampling back up):
     u_{L-1} = e_{L-1}
     b_l = R(conv(up(u_{l+1}))), u_l = R(conv(b_l + e_l))       l = L-2..0
     y   = conv(u_0)                                            one channel
-with R = max(0, .).  Inputs are three channels built from (d, N_pix, mask):
-d / sigma, log(N_pix / sigma^2) on observed pixels (0 on masked ones) and the
-mask, where sigma^2 is the mean white variance over observed pixels; the
-target is s / sigma.
+with R = max(0, .).  Inputs are four channels built from (d, N_pix, mask):
+d / sigma, log(N_pix / sigma^2) on observed pixels (0 on masked ones), the
+mask, and the mean of d / sigma over the observed pixels of the pixel's row
+(row-constant stripe noise is visible only over a whole row, wider than the
+network's receptive field), where sigma^2 is the mean white variance over
+observed pixels; the target is the field to predict divided by sigma.
 
 Pinned (tests, ``not gpu``) by: brute-force loops for the convolution, the
 adjoint identities <A x, y> = <x, A^T y> for convolution, pooling and
@@ -117,7 +119,7 @@ class Params:
         return Params([x.copy() for x in self.w], [x.copy() for x in self.b])
 
 
-def layer_shapes(channels: Sequence[int], c_in: int = 3) -> List[tuple]:
+def layer_shapes(channels: Sequence[int], c_in: int = 4) -> List[tuple]:
     """(Ci, Co) of each convolution: two per encoder level, two per decoder
     level, then the single-channel output convolution."""
     L = len(channels)
@@ -130,7 +132,7 @@ def layer_shapes(channels: Sequence[int], c_in: int = 3) -> List[tuple]:
     return shapes
 
 
-def init_params(channels: Sequence[int], seed: int, c_in: int = 3) -> Params:
+def init_params(channels: Sequence[int], seed: int, c_in: int = 4) -> Params:
     """He-normal weights (std sqrt(2 / (9 Ci))), zero biases; the output
     convolution starts at zero so the first prediction is 0 (the zero start)."""
     rng = np.random.default_rng(seed)
@@ -229,16 +231,19 @@ def backward(p: Params, tp: Tape, target: np.ndarray, channels: Sequence[int]) -
 # --------------------------------------------------------------------------
 
 def features(d: np.ndarray, n_pix: np.ndarray, mask: np.ndarray | None):
-    """Network inputs [H, W, 3] and the scale sigma (see the module notes)."""
+    """Network inputs [H, W, 4] and the scale sigma (see the module notes)."""
     d = np.asarray(d, dtype=np.float64)
     npix = np.asarray(n_pix, dtype=np.float64)
     obs = np.ones(d.shape, dtype=bool) if mask is None else np.asarray(mask) != 0
     sig2 = float(npix[obs].mean())
     sig = np.sqrt(sig2)
-    f = np.zeros(d.shape + (3,))
+    f = np.zeros(d.shape + (4,))
     f[..., 0] = np.where(obs, d / sig, 0.0)
     f[..., 1] = np.where(obs, np.log(np.where(obs, npix, 1.0) / sig2), 0.0)
     f[..., 2] = obs.astype(np.float64)
+    cnt = obs.sum(axis=1)
+    rows = np.where(cnt > 0, f[..., 0].sum(axis=1) / np.maximum(cnt, 1), 0.0)
+    f[..., 3] = rows[:, None]
     return f, sig
 
 

@@ -53,7 +53,8 @@ class _Schedule(ctypes.Structure):
                 ("snap_eps", ctypes.c_double), ("rtol", ctypes.c_double),
                 ("max_sweeps", ctypes.c_int32), ("monitor_every", ctypes.c_int32),
                 ("beta", ctypes.c_double * 3), ("floor_frac", ctypes.c_double),
-                ("chain", ctypes.c_int32), ("stop_full", ctypes.c_int32)]
+                ("chain", ctypes.c_int32), ("stop_full", ctypes.c_int32),
+                ("field_mode", ctypes.c_int32)]
 
 
 class _Report(ctypes.Structure):
@@ -98,7 +99,7 @@ def load():
     lib.wf_inverse_noise_weight.restype = i32
     lib.wf_solve_batch.argtypes = [ctypes.POINTER(vp), i32, ctypes.POINTER(_Inputs),
                                    ctypes.POINTER(_Schedule), ctypes.POINTER(vp),
-                                   ctypes.POINTER(_Report), vp]
+                                   ctypes.POINTER(vp), ctypes.POINTER(_Report), vp]
     lib.wf_solve_batch.restype = i32
     lib.wf_rfft2.argtypes = [vp, vp, vp, vp]
     lib.wf_rfft2.restype = i32
@@ -145,6 +146,7 @@ class Schedule:
     floor_frac: float = 0.5
     chain: str = "three"
     stop_full: bool = False
+    chain_field: bool = False
 
     def _c(self):
         s = _Schedule()
@@ -170,6 +172,7 @@ class Schedule:
         s.floor_frac = self.floor_frac
         s.chain = CHAINS[self.chain]
         s.stop_full = 1 if self.stop_full else 0
+        s.field_mode = 1 if self.chain_field else 0
         return s, keep
 
 
@@ -349,13 +352,15 @@ def solve(d, s_k, n_pix, p_oof=None, p_stripe=None, mask=None, *, schedule=Sched
         ctx.close()
 
 
-def solve_batch(contexts, problems, *, schedule: Schedule = Schedule(), outs=None):
+def solve_batch(contexts, problems, *, schedule: Schedule = Schedule(), outs=None,
+                s_inits=None):
     """Solve many maps at once (``wf_solve_batch``).  contexts: one distinct
     ``Context`` per map (same precision and device); problems: per map a dict
     with keys d, s_k, n_pix and optionally p_oof, p_stripe, mask (device
     tensors checked like ``Context.solve``).  Returns (list of maps, list of
     report dicts).  Maps of one shape share their kernel launches; one chunk
-    of sweeps is replayed as a HIP graph."""
+    of sweeps is replayed as a HIP graph.  s_inits: optional per-map warm
+    starts (device tensors of each map's shape, or None entries)."""
     import torch
     lib = load()
     n = len(contexts)
@@ -366,6 +371,7 @@ def solve_batch(contexts, problems, *, schedule: Schedule = Schedule(), outs=Non
     inps = (_Inputs * n)()
     handles = (ctypes.c_void_p * n)()
     optrs = (ctypes.c_void_p * n)()
+    iptrs = (ctypes.c_void_p * n)()
     res = []
     for i, (ctx, pb) in enumerate(zip(contexts, problems)):
         ny, nx = ctx.ny, ctx.nx
@@ -385,11 +391,16 @@ def solve_batch(contexts, problems, *, schedule: Schedule = Schedule(), outs=Non
                           pb.get("p_stripe"), pb.get("mask"))
         handles[i] = ctx._h
         optrs[i] = o.data_ptr()
+        si = None if s_inits is None else s_inits[i]
+        if si is not None:
+            ctx._check(si, (ny, nx), "s_init")
+            iptrs[i] = si.data_ptr()
     sch, keep = schedule._c()
     reps = (_Report * n)()
     dev = contexts[0].device
     with torch.cuda.device(dev):
-        st = lib.wf_solve_batch(handles, n, inps, ctypes.byref(sch), optrs, reps,
+        st = lib.wf_solve_batch(handles, n, inps, ctypes.byref(sch),
+                                iptrs if s_inits is not None else None, optrs, reps,
                                 _stream_ptr(torch, dev))
     del keep
     if st < 0:

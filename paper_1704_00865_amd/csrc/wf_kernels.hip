@@ -644,7 +644,8 @@ __global__ __launch_bounds__(TC * (NY / elems<NY>::value), (min_waves<T, NY>()))
   if constexpr (MODE == COL_INIT) {
     // warm start: every stored field = s_init; the field handed to the white
     // level is s_init too, except for a chain without Fourier level, where it
-    // is the signal-end field S_c (S_c + lambda_0 tau)^-1 s_init
+    // is the signal-end field S_c (S_c + lambda_0 tau)^-1 s_init (or s_init
+    // itself when s_init is that field)
     cx<T>* tA = (cx<T>*)a.tA;
     cx<T>* dA = (cx<T>*)a.dA;
     cx<T>* tB = (cx<T>*)a.tB;
@@ -660,8 +661,10 @@ __global__ __launch_bounds__(TC * (NY / elems<NY>::value), (min_waves<T, NY>()))
         const size_t idx = (size_t)kx * NY + ky;
         cx<T> v = h == 0 ? reg[q] : cnl[lpad(ky)];
         if (a.fk == FK_NONE) {
-          const T s = a.sc[idx];
-          v = cscale(v, s / (s + TW0));
+          if (!a.warm_chain) {
+            const T s = a.sc[idx];
+            v = cscale(v, s / (s + TW0));
+          }
         } else {
           tA[idx] = v;
           if (a.fk == FK_ARRAY_STRIPE) {
@@ -732,7 +735,8 @@ __global__ __launch_bounds__(kTCM * (NY / elems<NY>::value)) void mon_col_kernel
       const cx<T> v = tf[idx];
       const double inv = 1.0 / ((double)m.sc[idx] + Tf);
       const cx<double> x = {(double)v.re * inv, (double)v.im * inv};
-      const double f = (mode == MON_OUTPUT) ? (double)m.sig[idx] : (double)m.sy[idx];
+      const double f = (mode == MON_OUTPUT) ? (m.out_chain ? (double)m.sc[idx] : (double)m.sig[idx])
+                                            : (double)m.sy[idx];
       rx[q] = x;
       ry[q] = cx<double>{x.re * f, x.im * f};
     } else {

@@ -66,6 +66,7 @@ struct SweepArgs {
   double tauA, tauB, tauW;  // messenger variances (A: signal-side level)
   double cB;              // Nbar offset of a stripe level (phi - tau)
   double scale;           // 1 / (nx ny)
+  int32_t warm_chain;     // warm start gives the chain's signal-end field itself
 };
 
 // per-mode coefficient preparation (see prep_spectra_kernel)
@@ -98,6 +99,7 @@ struct MonArgs {
   int nx, ny, kpm;      // kpm: padded half width (multiple of kTCM)
   double tau_first;
   double scale;
+  int32_t out_chain;    // output u = S_chain x instead of s = S x
 };
 
 // per-map arguments of the controller (one block per map)

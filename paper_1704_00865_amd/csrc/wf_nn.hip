@@ -295,18 +295,48 @@ __global__ __launch_bounds__(256) void sigma_kernel(const T* __restrict__ npix,
   if (threadIdx.x == 0) sig2[blockIdx.x] = sc[0] > 0 ? ss[0] / sc[0] : 1.0;
 }
 
-// x [P][32] bf16: d/sigma, log(N/sigma^2), mask, zeros; tgt[p] = s/sigma
+// rowm[r] = mean over the observed pixels of row r (of all maps) of d, or 0
+template <class T>
+__global__ __launch_bounds__(256) void rowmean_kernel(const T* __restrict__ d,
+                                                      const uint8_t* __restrict__ mask, int w,
+                                                      double* __restrict__ rowm) {
+  __shared__ double ss[256], sc[256];
+  const int64_t base = (int64_t)blockIdx.x * w;
+  double s = 0.0, c = 0.0;
+  for (int i = threadIdx.x; i < w; i += blockDim.x) {
+    if (mask ? mask[base + i] != 0 : true) {
+      s += (double)d[base + i];
+      c += 1.0;
+    }
+  }
+  ss[threadIdx.x] = s;
+  sc[threadIdx.x] = c;
+  __syncthreads();
+  for (int k = 128; k > 0; k >>= 1) {
+    if (threadIdx.x < k) {
+      ss[threadIdx.x] += ss[threadIdx.x + k];
+      sc[threadIdx.x] += sc[threadIdx.x + k];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) rowm[blockIdx.x] = sc[0] > 0 ? ss[0] / sc[0] : 0.0;
+}
+
+// x [P][32] bf16: d/sigma, log(N/sigma^2), mask, row mean of d/sigma, zeros;
+// tgt[p] = s/sigma
 template <class T>
 __global__ void features_kernel(const T* __restrict__ d, const T* __restrict__ npix,
                                 const uint8_t* __restrict__ mask, const T* __restrict__ s,
-                                const double* __restrict__ sig2, int64_t hw, int64_t P,
-                                uint16_t* __restrict__ x, float* __restrict__ tgt) {
+                                const double* __restrict__ sig2, const double* __restrict__ rowm,
+                                int w, int64_t hw, int64_t P, uint16_t* __restrict__ x,
+                                float* __restrict__ tgt) {
   for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < P;
        p += (int64_t)gridDim.x * blockDim.x) {
     const double v2 = sig2[p / hw];
     const double sg = sqrt(v2);
     const bool o = mask ? mask[p] != 0 : true;
     float f[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    f[3] = (float)(rowm[p / w] / sg);
     if (o) {
       f[0] = (float)((double)d[p] / sg);
       f[1] = (float)log((double)npix[p] / v2);
@@ -320,11 +350,11 @@ __global__ void features_kernel(const T* __restrict__ d, const T* __restrict__ n
   }
 }
 
-// x [P][32] bf16 from caller features [P][3] float
-__global__ void raw_features_kernel(const float* __restrict__ f3, int64_t P, uint16_t* __restrict__ x) {
+// x [P][32] bf16 from caller features [P][4] float
+__global__ void raw_features_kernel(const float* __restrict__ f4, int64_t P, uint16_t* __restrict__ x) {
   for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < P;
        p += (int64_t)gridDim.x * blockDim.x) {
-    float f[8] = {f3[3 * p], f3[3 * p + 1], f3[3 * p + 2], 0.f, 0.f, 0.f, 0.f, 0.f};
+    float f[8] = {f4[4 * p], f4[4 * p + 1], f4[4 * p + 2], f4[4 * p + 3], 0.f, 0.f, 0.f, 0.f};
     uint4* row = (uint4*)(x + p * kPad);
     row[0] = pack8(f);
     const uint4 z = {0u, 0u, 0u, 0u};
@@ -533,6 +563,7 @@ struct Net {
   float* yf = nullptr;                   // [P_0]
   float* tgt = nullptr;                  // [P_0]
   double* sig2 = nullptr;                // [nmax]
+  double* rowm = nullptr;                // [nmax * h] row means of d
   float* part = nullptr;                 // weight-gradient chunk partials
   double* lpart = nullptr;               // loss partials
   double* loss = nullptr;
@@ -603,6 +634,7 @@ wf_status create_net(const wf_nn_shape* s, Net** out) {
   NA(n->yf, P0 * 4);
   NA(n->tgt, P0 * 4);
   NA(n->sig2, n->nmax * 8);
+  NA(n->rowm, (size_t)n->nmax * n->h * 8);
   NA(n->part, (size_t)64 * 9 * 128 * 128 * 4);
   NA(n->lpart, 1024 * 8);
   NA(n->loss, 8);
@@ -727,8 +759,9 @@ wf_status prepare(Net* n, int nb, const void* d, const void* npix, const uint8_t
                   hipStream_t st) {
   const int64_t hw = (int64_t)n->h * n->w, P0 = nb * hw;
   hipLaunchKernelGGL(sigma_kernel<T>, dim3(nb), dim3(256), 0, st, (const T*)npix, mask, hw, n->sig2);
+  hipLaunchKernelGGL(rowmean_kernel<T>, dim3(nb * n->h), dim3(256), 0, st, (const T*)d, mask, n->w, n->rowm);
   hipLaunchKernelGGL(features_kernel<T>, dim3(grid_for(P0)), dim3(256), 0, st, (const T*)d, (const T*)npix,
-                     mask, (const T*)s, n->sig2, hw, P0, n->x, s ? n->tgt : nullptr);
+                     mask, (const T*)s, n->sig2, n->rowm, n->w, hw, P0, n->x, s ? n->tgt : nullptr);
   NN_TRY(hipGetLastError());
   return WF_OK;
 }

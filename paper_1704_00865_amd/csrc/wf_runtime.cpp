@@ -338,6 +338,7 @@ MonArgs<T> mon_args(Ctx* c, const wf_inputs* in, const Chain& ch) {
 
 wf_status check_schedule(const wf_schedule* s) {
   if (s->max_sweeps < 1 || s->monitor_every < 1) return WF_EINVAL;
+  if (s->field_mode != 0 && s->field_mode != 1) return WF_EINVAL;
   if (s->kind == WF_SCHED_FIXED) {
     if (!s->lambda || s->n_lambda < 1) return WF_EINVAL;
     for (int i = 0; i < s->n_lambda; ++i)
@@ -449,9 +450,11 @@ wf_status map_setup(Ctx* c, const wf_inputs* in, const wf_schedule* s, const voi
   WF_TRY(hipMemcpyAsync(dsched, &h, sizeof(h), hipMemcpyHostToDevice, st));
   r.a = sweep_args<T>(c, in, r.ch);
   r.a.sch = dsched;
+  r.a.warm_chain = s->field_mode;
   r.m = mon_args<T>(c, in, r.ch);
   r.m.sch = dsched;
   r.m.s_out = s_out;
+  r.m.out_chain = s->field_mode;
   r.ctrl = CtrlArgs{dsched, c->lam, c->part, c->ny / kTRM, c->trace};
   // initial state (the single-map argument block is used for the warm start)
   const size_t modes_b = (size_t)c->nh * c->ny * 2 * c->esz;
@@ -602,7 +605,8 @@ wf_status solve_t(Ctx* c, const wf_inputs* in, const wf_schedule* s, const void*
 // chunk of sweeps is captured once in a HIP graph and replayed.
 template <class T>
 wf_status solve_batch_t(Ctx** ctxs, int n, const wf_inputs* ins, const wf_schedule* s,
-                        void* const* s_out, wf_report* reps, hipStream_t user_st) {
+                        const void* const* s_init, void* const* s_out, wf_report* reps,
+                        hipStream_t user_st) {
   std::vector<MapRun<T>> runs(n);
   // device buffers of this call: schedules, argument blocks, controller args
   DevSched* dsch = nullptr;
@@ -642,7 +646,8 @@ wf_status solve_batch_t(Ctx** ctxs, int n, const wf_inputs* ins, const wf_schedu
   BT(hipMalloc((void**)&dctrl, (size_t)n * sizeof(CtrlArgs)));
   BT(hipHostMalloc((void**)&hring, (size_t)kRing * n * sizeof(DevSched), hipHostMallocDefault));
   for (int i = 0; i < n; ++i) {
-    wf_status ms = map_setup<T>(ctxs[i], &ins[i], s, nullptr, s_out[i], dsch + i, runs[i], user_st);
+    wf_status ms = map_setup<T>(ctxs[i], &ins[i], s, s_init ? s_init[i] : nullptr, s_out[i],
+                                dsch + i, runs[i], user_st);
     if (ms != WF_OK) {
       (void)hipStreamSynchronize(user_st);
       cleanup();
@@ -794,6 +799,7 @@ void wf_schedule_default(wf_schedule* s) {
   s->floor_frac = 0.5;
   s->chain = WF_CHAIN_THREE;
   s->stop_full = 0;
+  s->field_mode = 0;
 }
 
 wf_status wf_solve(void* ctx, const wf_inputs* in, const wf_schedule* sch, const void* s_init,
@@ -809,8 +815,8 @@ wf_status wf_solve(void* ctx, const wf_inputs* in, const wf_schedule* sch, const
 }
 
 wf_status wf_solve_batch(void* const* ctxs, int32_t n, const wf_inputs* inputs,
-                         const wf_schedule* sch, void* const* s_out, wf_report* reps,
-                         hipStream_t stream) {
+                         const wf_schedule* sch, const void* const* s_init, void* const* s_out,
+                         wf_report* reps, hipStream_t stream) {
   if (!ctxs || !inputs || !sch || !s_out || n < 1 || n > WF_BATCH_MAX) return WF_EINVAL;
   wf_status v = check_schedule(sch);
   if (v != WF_OK) return v;
@@ -826,8 +832,9 @@ wf_status wf_solve_batch(void* const* ctxs, int32_t n, const wf_inputs* inputs,
       if (cs[j] == c) return WF_EINVAL;  // each map needs its own context
     cs[i] = c;
   }
-  if (cs[0]->prec == WF_F64) return solve_batch_t<double>(cs.data(), n, inputs, sch, s_out, reps, stream);
-  return solve_batch_t<float>(cs.data(), n, inputs, sch, s_out, reps, stream);
+  if (cs[0]->prec == WF_F64)
+    return solve_batch_t<double>(cs.data(), n, inputs, sch, s_init, s_out, reps, stream);
+  return solve_batch_t<float>(cs.data(), n, inputs, sch, s_init, s_out, reps, stream);
 }
 
 wf_status wf_inverse_noise_weight(void* ctx, const wf_inputs* in, double alpha,
@@ -836,6 +843,7 @@ wf_status wf_inverse_noise_weight(void* ctx, const wf_inputs* in, double alpha,
   Ctx* c = (Ctx*)ctx;
   if (!c || !in || !sch || !out || !in->d || !in->n_pix) return WF_EINVAL;
   if (!(alpha > 0) || !std::isfinite(alpha)) return WF_EINVAL;
+  if (sch->field_mode != 0) return WF_EINVAL;
   const int64_t nmodes = (int64_t)c->ny * c->nh;
   if (!c->alpha_sk) {
     wf_status as = alloc(&c->alpha_sk, (size_t)nmodes * c->esz);

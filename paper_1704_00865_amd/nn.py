@@ -96,7 +96,7 @@ def init_params(seed: int = 0) -> np.ndarray:
     for i, (ci, co, wo, _) in enumerate(offs):
         if i == len(offs) - 1:
             continue
-        ci_real = 3 if i == 0 else ci
+        ci_real = 4 if i == 0 else ci
         w = np.zeros((3, 3, ci, co))
         w[:, :, :ci_real, :] = rng.standard_normal((3, 3, ci_real, co)) * np.sqrt(2.0 / (9 * ci_real))
         p[wo:wo + w.size] = w.ravel()
@@ -197,8 +197,8 @@ class WarmNet:
     def forward_features(self, x):
         import torch
         n = x.shape[0]
-        if x.shape != (n, self.h, self.w, 3) or x.dtype != torch.float32:
-            raise ValueError("x must be float32 [n, h, w, 3]")
+        if x.shape != (n, self.h, self.w, 4) or x.dtype != torch.float32:
+            raise ValueError("x must be float32 [n, h, w, 4]")
         y = torch.empty((n, self.h, self.w), dtype=torch.float32, device=self.device)
         self._call("wf_nn_forward_features", n, x.contiguous().data_ptr(), y.data_ptr(), self._st())
         return y

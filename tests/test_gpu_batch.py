@@ -163,3 +163,26 @@ def test_survey_batch_shapes(gpu_lib):
     res = oracle.solve(probs[3], oracle.FixedSchedule(lams), max_sweeps=len(lams),
                        monitor_every=8)
     assert _rel(outs[3].astype(np.float64), res.s) < TOL["f32"]
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_batch_warm_starts_match_single(gpu_lib, prec):
+    """Per-map warm starts (one entry None) give the single solves' results."""
+    import torch
+    probs = [synth.make_problem(64, 64, 81, mask_frac=0.1), synth.make_problem(64, 64, 82),
+             synth.make_problem(128, 64, 83)]
+    dt = torch.float32 if prec == "f32" else torch.float64
+    inits = [torch.tensor(probs[0].s_true, dtype=dt, device="cuda"), None,
+             torch.tensor(0.5 * probs[2].s_true, dtype=dt, device="cuda")]
+    sched = gpu_lib.Schedule(lambdas=list(oracle.cooling_ramp(6, 12, 50.0)), rtol=0.0,
+                             max_sweeps=12, monitor_every=4, chain="augmented")
+    ctxs = [gpu_lib.Context(p.d.shape[0], p.d.shape[1], prec) for p in probs]
+    outs, reps = gpu_lib.solve_batch(ctxs, [_dict(p, prec) for p in probs], schedule=sched,
+                                     s_inits=inits)
+    for i, p in enumerate(probs):
+        ny, nx = p.d.shape
+        ctx = gpu_lib.Context(ny, nx, prec)
+        pb = _dict(p, prec)
+        s1, _, _ = ctx.solve(pb["d"], pb["s_k"], pb["n_pix"], pb["p_oof"], pb["p_stripe"],
+                             pb.get("mask"), schedule=sched, s_init=inits[i])
+        assert torch.equal(outs[i], s1), i

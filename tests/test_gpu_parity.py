@@ -27,7 +27,7 @@ def _tensors(p, prec, device="cuda"):
 
 
 def _run_both(gpu_lib, p, prec, lams, *, chain="three", beta=(0.9, 0.9, 1.0), floor_frac=0.5,
-              monitor_every=8, s_init=None):
+              monitor_every=8, s_init=None, chain_field=False):
     import torch
     ny, nx = p.d.shape
     print(f"parity {prec} {ny}x{nx} chain={chain} sweeps={len(lams)} "
@@ -36,7 +36,7 @@ def _run_both(gpu_lib, p, prec, lams, *, chain="three", beta=(0.9, 0.9, 1.0), fl
     ctx = gpu_lib.Context(ny, nx, prec)
     sched = gpu_lib.Schedule(lambdas=list(lams), rtol=0.0, max_sweeps=len(lams),
                              monitor_every=monitor_every, beta=beta, floor_frac=floor_frac,
-                             chain=chain)
+                             chain=chain, chain_field=chain_field)
     args = _tensors(p, prec)
     si = None
     if s_init is not None:
@@ -46,7 +46,8 @@ def _run_both(gpu_lib, p, prec, lams, *, chain="three", beta=(0.9, 0.9, 1.0), fl
     si_np = None if si is None else si.cpu().numpy().astype(np.float64)
     res = oracle.solve(p, oracle.FixedSchedule(list(lams)),
                        settings=oracle.Settings(beta=beta, floor_frac=floor_frac, chain=chain),
-                       s_init=si_np, max_sweeps=len(lams), monitor_every=monitor_every)
+                       s_init=si_np, max_sweeps=len(lams), monitor_every=monitor_every,
+                       chain_field=chain_field)
     return s_gpu, rep, trace, res
 
 
@@ -112,6 +113,20 @@ def test_warm_start_parity(gpu_lib, prec, chain):
     s_init = np.asarray(p.s_true, dtype=np.float32 if prec == "f32" else np.float64)
     s_gpu, rep, trace, res = _run_both(gpu_lib, p, prec, _ramp(10, 20, 50.0), chain=chain,
                                        s_init=s_init)
+    assert _rel(s_gpu, res.s) < TOL[prec]
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+@pytest.mark.parametrize("chain", ["three", "augmented"])
+@pytest.mark.parametrize("warm", [False, True])
+def test_chain_field_mode_parity(gpu_lib, prec, chain, warm):
+    """field_mode 1: warm start and output are the chain's signal-end field."""
+    p = synth.make_problem(64, 128, 10, mask_frac=0.1)
+    s_init = None
+    if warm:
+        s_init = np.asarray(1.1 * p.s_true, dtype=np.float32 if prec == "f32" else np.float64)
+    s_gpu, rep, trace, res = _run_both(gpu_lib, p, prec, _ramp(10, 20, 20.0), chain=chain,
+                                       s_init=s_init, chain_field=True)
     assert _rel(s_gpu, res.s) < TOL[prec]
 
 

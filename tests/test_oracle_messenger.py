@@ -373,3 +373,51 @@ def test_masked_pixels_are_ignored():
     q.n_pix = np.where(q.mask == 0, -5.0, q.n_pix)
     r2 = oracle.solve(q, oracle.FixedSchedule(oracle.cooling_ramp(20, 40, 1e3)), max_sweeps=40)
     np.testing.assert_array_equal(r1.s, r2.s)
+
+
+def _chain_field_dense(p, chain):
+    """u = S_chain x with x = S^-1 s from the dense Cholesky solve; S_chain is
+    S + N_1/f + N_stripe for the augmented chain (built here from dense
+    circulant and stripe matrices) and S otherwise."""
+    ny, nx = p.d.shape
+    x = direct.wiener_dense_x(p).ravel()
+    Sc = direct.stationary_cov_dense(p.s_k, nx)
+    if chain == "augmented":
+        Sc = Sc + direct.stationary_cov_dense(p.p_oof, nx) + direct.stripe_cov_dense(p.p_stripe, nx)
+    return (Sc @ x).reshape(ny, nx)
+
+
+@pytest.mark.parametrize("mask", [False, True])
+def test_chain_field_output_and_exact_warm_start(mask):
+    """Augmented chain: the chain-field output of a converged solve is
+    (S + N_F) x with x from the dense Cholesky solve, and starting from that
+    field at lambda = 1 is already the fixed point (no sweep moves it)."""
+    p = _easy_three_term(mask=mask)
+    st = oracle.setup(p, oracle.Settings(chain="augmented"))
+    if st.phi > 0:
+        pytest.skip("stripe floor without a 1/f partner changes S_chain")
+    ud = _chain_field_dense(p, "augmented")
+    r = oracle.solve(p, oracle.AdaptiveSchedule(lam0=1e3, plateau=1e-3),
+                     settings=oracle.Settings(chain="augmented"), max_sweeps=40000,
+                     monitor_every=4, rtol=1e-12, full_residual=True, chain_field=True)
+    assert r.converged
+    assert np.linalg.norm(r.s - ud) / np.linalg.norm(ud) < 1e-9
+    w = oracle.solve(p, oracle.FixedSchedule([1.0]), settings=oracle.Settings(chain="augmented"),
+                     s_init=ud, max_sweeps=5, monitor_every=1, chain_field=True)
+    assert w.trace[0][2] < 1e-9
+    assert np.linalg.norm(w.s - ud) / np.linalg.norm(ud) < 1e-9
+    # the signal-mode warm start from the same field is not at the fixed point
+    v = oracle.solve(p, oracle.FixedSchedule([1.0]), settings=oracle.Settings(chain="augmented"),
+                     s_init=ud, max_sweeps=1, monitor_every=1)
+    assert v.trace[0][2] > 1e-6
+
+
+def test_chain_field_is_the_signal_for_chains_with_a_fourier_level():
+    p = _easy_three_term(mask=True)
+    lams = list(oracle.cooling_ramp(10, 20, 30.0))
+    a = oracle.solve(p, oracle.FixedSchedule(lams), s_init=p.s_true, max_sweeps=20)
+    b = oracle.solve(p, oracle.FixedSchedule(lams), s_init=p.s_true, max_sweeps=20, chain_field=True)
+    # the same iterates; the two outputs differ only in rounding (S x formed
+    # with one or two transforms)
+    assert [t[2] for t in a.trace] == [t[2] for t in b.trace]
+    assert np.linalg.norm(a.s - b.s) / np.linalg.norm(a.s) < 1e-13

@@ -74,7 +74,7 @@ def test_network_gradient_matches_finite_differences():
     p.w[-1] = rng.standard_normal(p.w[-1].shape) * 0.3
     for b in p.b:
         b[:] = rng.standard_normal(b.shape) * 0.1
-    x = rng.standard_normal((2, 16, 16, 3))
+    x = rng.standard_normal((2, 16, 16, 4))
     tgt = rng.standard_normal((2, 16, 16))
     tp = wn.forward(p, x, ch)
     g = wn.backward(p, tp, tgt, ch)
@@ -98,10 +98,10 @@ def test_layer_shapes_and_zero_initial_prediction():
     ch = (32, 64, 96, 128)
     shapes = wn.layer_shapes(ch)
     assert len(shapes) == 15
-    assert shapes[0] == (3, 32) and shapes[-1] == (32, 1)
+    assert shapes[0] == (4, 32) and shapes[-1] == (32, 1)
     assert shapes[8] == (128, 96) and shapes[13] == (32, 32)
     p = wn.init_params((4, 4, 4, 4), seed=0)
-    y = wn.forward(p, _rng(0).standard_normal((1, 16, 16, 3)), (4, 4, 4, 4)).y
+    y = wn.forward(p, _rng(0).standard_normal((1, 16, 16, 4)), (4, 4, 4, 4)).y
     assert np.all(y == 0.0)
 
 
@@ -115,8 +115,12 @@ def test_features_scale_invariance_and_mask():
     f2, sig2 = wn.features(3.0 * d, 9.0 * npix, mask)
     assert sig2 == pytest.approx(3.0 * sig)
     assert np.allclose(f, f2, atol=1e-12)
-    assert np.all(f[mask == 0] == 0.0)
+    assert np.all(f[mask == 0][:, :3] == 0.0)
     assert np.all(f[mask == 1, 2] == 1.0)
+    # row channel: mean of the observed d / sigma of the row, on every pixel
+    y = 5
+    obs = mask[y] == 1
+    assert np.allclose(f[y, :, 3], (d[y, obs] / sig).mean())
 
 
 def test_adam_first_step_moves_by_lr_times_sign():
