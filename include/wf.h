@@ -80,7 +80,8 @@ typedef struct {         /* DEVICE pointers, caller-owned, read-only during the 
   const void* d;         /* [ny*nx] data                                          */
   const void* s_k;       /* [ny*(nx/2+1)] signal mode variance, >= 0              */
   const void* n_pix;     /* [ny*nx] white variance, > 0 on observed pixels        */
-  const void* p_oof;     /* [ny*(nx/2+1)] 1/f mode variance >= 0, or NULL (absent)*/
+  const void* p_oof;     /* [ny*(nx/2+1)] 1/f mode variance >= 0, or NULL (absent);*/
+                         /*   +inf projects that mode out of the data (Section 4)  */
   const void* p_stripe;  /* [ny] stripe 1-D mode variance >= 0, or NULL (absent)  */
   const uint8_t* mask;   /* [ny*nx] 1 observed / 0 masked, or NULL (all observed) */
 } wf_inputs;

@@ -18,6 +18,8 @@ so S^-1 is useless numerically.  Dense solves are for maps up to 64x64.
 
 from __future__ import annotations
 
+import dataclasses
+
 import numpy as np
 import scipy.linalg as sla
 
@@ -93,6 +95,40 @@ def wiener_dense_x(problem, refine: int = 2) -> np.ndarray:
     x = np.zeros(problem.d.size)
     x[P] = z
     return x.reshape(problem.d.shape)
+
+
+def wiener_projected_dense(problem) -> np.ndarray:
+    """Wiener filter with infinite noise variance on the Fourier modes where
+    the 1/f spectrum is +inf (those modes are projected out of the data,
+    Section 4) and on masked pixels, as the exact limit:
+        x = Z (Z^T (S + N_f) Z)^-1 Z^T d,   s = S x,
+    where N_f is the finite part of N and Z an orthonormal basis of the maps
+    that vanish on masked pixels and have no component along the projected
+    modes (real and imaginary parts of their unitary DFT vectors)."""
+    ny, nx = problem.d.shape
+    n = ny * nx
+    p = np.asarray(problem.p_oof, dtype=np.float64)
+    flag = np.isinf(p)
+    fin = dataclasses.replace(problem, p_oof=np.where(flag, 0.0, p))
+    S, Nf = dense_covariances(fin)
+    full = full_from_half(flag.astype(np.float64), nx) > 0.5
+    y = np.repeat(np.arange(ny), nx)
+    x = np.tile(np.arange(nx), ny)
+    vecs = []
+    for ky, kx in zip(*np.nonzero(full)):
+        e = np.exp(2j * np.pi * (ky * y / ny + kx * x / nx)) / np.sqrt(n)
+        vecs += [e.real, e.imag]
+    cols = [np.stack(vecs, axis=1)] if vecs else []
+    obs = np.ones(n, bool) if problem.mask is None else np.asarray(problem.mask).ravel() != 0
+    masked = np.flatnonzero(~obs)
+    if masked.size:
+        cols.append(np.eye(n)[:, masked])
+    C = np.concatenate(cols, axis=1)
+    Z = sla.null_space(C.T)
+    A = S + Nf
+    d = np.asarray(problem.d, dtype=np.float64).ravel()
+    xs = Z @ np.linalg.solve(Z.T @ A @ Z, Z.T @ d)
+    return (S @ xs).reshape(ny, nx)
 
 
 def chi2_dense(problem, s: np.ndarray) -> float:

@@ -90,10 +90,22 @@ class Setup:
     chain: str = "three"
 
 
-def _check_spectrum(name, p):
+# An infinite noise variance on a Fourier mode projects the mode out of the
+# data (Section 4).  It is carried as this finite value, which every update of
+# the multiplied form [B a + A b] / (A + B) turns into its A -> inf limit b up
+# to a relative 1e-30 * (largest other covariance).
+INFINITE_COV = 1.0e30
+
+
+def _check_spectrum(name, p, allow_inf=False):
     p = np.asarray(p, dtype=np.float64)
-    if not np.all(np.isfinite(p)) or np.any(p < 0):
-        raise InvalidInput(f"{name} must be finite and >= 0")
+    bad = np.isnan(p) | (p < 0) | (np.isinf(p) if not allow_inf else False)
+    if np.any(bad):
+        raise InvalidInput(f"{name} must be >= 0 and finite" + (" or +inf" if allow_inf else ""))
+    if allow_inf:
+        if np.all(np.isinf(p)):
+            raise InvalidInput(f"{name}: every mode projected out")
+        p = np.where(np.isinf(p), INFINITE_COV, p)
     return p
 
 
@@ -124,7 +136,8 @@ def setup(problem, settings: Settings = Settings()) -> Setup:
     if not (np.all(np.isfinite(d[obs])) and np.all(np.isfinite(n_pix[obs]))):
         raise InvalidInput("non-finite data or pixel variance")
     s_k = _check_spectrum("signal spectrum", problem.s_k)
-    p_oof = None if problem.p_oof is None else _check_spectrum("1/f spectrum", problem.p_oof)
+    p_oof = (None if problem.p_oof is None
+             else _check_spectrum("1/f spectrum", problem.p_oof, allow_inf=True))
     p_st = None if problem.p_stripe is None else _check_spectrum("stripe spectrum", problem.p_stripe)
     b0, b1, b2 = settings.beta
     S = FourierDiag(s_k, (ny, nx))
@@ -253,13 +266,21 @@ def diagnostics(st: Setup, x: State, lam: float) -> Diagnostics:
     observed part alone can be tiny while the masked region is still far from
     converged."""
     T0 = lam * st.levels[0].tau
-    xs = st.S_chain.apply_fn(lambda e: 1.0 / (e + T0), x.t[0])
-    rec = st.S_chain.apply(xs)
+    xk = rfft2u(x.t[0]) / (st.S_chain.eig + T0)
+    xs = irfft2u(xk, st.shape)
+    # terms diagonal in the 2-D Fourier basis act on x's modes directly (a
+    # round trip of x through pixel space would put rounding noise on every
+    # mode, which a projected mode's 1e30 variance would then amplify)
+    fsum = st.S_chain.eig.copy()
+    rec = np.zeros(st.shape)
     for l in st.levels:
         if isinstance(l.n_true, PixelDiag):
             rec += np.where(st.observed, l.n_true.eig * xs, 0.0)
+        elif isinstance(l.n_true, FourierDiag):
+            fsum = fsum + l.n_true.eig
         else:
             rec += l.n_true.apply(xs)
+    rec += irfft2u(fsum * xk, st.shape)
     obs = st.observed
     dd = np.where(obs, rec - st.d, 0.0)
     d2 = float(np.sum(st.d[obs] ** 2))

@@ -134,7 +134,7 @@ __global__ __launch_bounds__(256) void stats_spectra_kernel(const T* __restrict_
     double f = 0;
     if (poof) {
       const double o = (double)poof[i];
-      if (!isfinite(o) || o < 0) bo += 1;
+      if (isnan(o) || o < 0) bo += 1;  // +inf is allowed: a projected mode
       mo = fmin(mo, o);
       f = o;
     }
@@ -210,7 +210,8 @@ __global__ __launch_bounds__(256) void prep_spectra_kernel(const T* __restrict__
     const int kx = (int)(j / a.ny), ky = (int)(j - (int64_t)kx * a.ny);
     const int64_t i = (int64_t)ky * nh + kx;  // row-major source index
     const double s = (double)sk[i];
-    const double o = a.has_oof ? (double)poof[i] : 0.0;
+    double o = a.has_oof ? (double)poof[i] : 0.0;
+    if (isinf(o)) o = kInfiniteCov;  // projected mode (see kInfiniteCov)
     const double st = (a.has_st && kx == 0) ? (double)a.nx * (double)pst[ky] : 0.0;
     const double nf = o + st;
     sc[j] = (T)(a.sc_adds_nf ? s + nf + a.phi_nf : s);

@@ -70,6 +70,13 @@ struct SweepArgs {
 };
 
 // per-mode coefficient preparation (see prep_spectra_kernel)
+// An infinite noise variance on a Fourier mode (a 1/f spectrum entry of
+// +inf) projects that mode out of the data (Section 4).  It is carried as
+// this finite value: every update of the multiplied form then takes its
+// limit up to a relative 1e-30 * (largest other covariance), and every
+// product stays finite in float32.
+constexpr double kInfiniteCov = 1.0e30;
+
 struct PrepSpecArgs {
   int ny, nx;
   int has_oof, has_st;

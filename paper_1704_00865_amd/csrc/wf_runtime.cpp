@@ -223,6 +223,7 @@ wf_status plan_chain(const Ctx* c, const wf_schedule* s, bool has_oof, bool has_
                      const double* pix, const double* spec, Chain* ch) {
   const double min_npix = pix[1];
   const double min_oof = spec[1];
+  if (has_oof && !std::isfinite(min_oof)) return WF_EINVAL;  // every mode projected out
   const double min_nf = spec[2];  // min over modes of (P_1/f or 0) + nx P_st delta_kx0
   const double b0 = s->beta[0], b1 = s->beta[1], b2 = s->beta[2];
   const double alpha = s->floor_frac;

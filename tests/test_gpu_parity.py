@@ -131,6 +131,33 @@ def test_chain_field_mode_parity(gpu_lib, prec, chain, warm):
 
 
 @pytest.mark.parametrize("prec", ["f64", "f32"])
+@pytest.mark.parametrize("chain", ["three", "merged", "augmented"])
+def test_projected_modes_parity(gpu_lib, prec, chain):
+    """A 1/f variance of +inf projects a Fourier mode out of the data."""
+    import dataclasses
+    p = synth.make_problem(64, 64, 12, mask_frac=0.1)
+    po = np.array(p.p_oof)
+    for ky, kx in [(0, 0), (1, 0), (63, 0), (0, 1), (1, 1), (63, 1)]:
+        po[ky, kx] = np.inf
+    p = dataclasses.replace(p, p_oof=po)
+    s_gpu, rep, trace, res = _run_both(gpu_lib, p, prec, _ramp(20, 40), chain=chain,
+                                       monitor_every=8)
+    assert np.all(np.isfinite(s_gpu))
+    assert _rel(s_gpu, res.s) < TOL[prec]
+
+
+def test_projected_every_mode_is_rejected(gpu_lib):
+    import torch
+    p = synth.make_problem(64, 64, 13)
+    args = list(_tensors(p, "f64"))
+    args[3] = torch.full_like(args[3], float("inf"))
+    ctx = gpu_lib.Context(64, 64, "f64")
+    with pytest.raises(gpu_lib.WFError) as e:
+        ctx.solve(*args, schedule=gpu_lib.Schedule(lambdas=[1.0], max_sweeps=1, rtol=0.0))
+    assert e.value.status == -1
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
 def test_single_sweep_and_ragged_chunk(gpu_lib, prec):
     """max_sweeps = 1, and a budget that is not a multiple of the monitor
     interval (the last chunk is partial)."""

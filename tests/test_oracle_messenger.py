@@ -421,3 +421,70 @@ def test_chain_field_is_the_signal_for_chains_with_a_fourier_level():
     # with one or two transforms)
     assert [t[2] for t in a.trace] == [t[2] for t in b.trace]
     assert np.linalg.norm(a.s - b.s) / np.linalg.norm(a.s) < 1e-13
+
+
+def _projected(p, modes):
+    """Copy of p with the 1/f variance of the given half-spectrum modes set
+    to +inf (projected out)."""
+    import dataclasses
+    po = np.array(p.p_oof, dtype=np.float64)
+    for ky, kx in modes:
+        po[ky, kx] = np.inf
+    return dataclasses.replace(p, p_oof=po)
+
+
+LOW_MODES = [(0, 0), (1, 0), (31, 0), (0, 1), (1, 1), (31, 1)]
+
+
+@pytest.mark.parametrize("chain,mask", [("augmented", True), ("augmented", False),
+                                        ("three", False)])
+def test_projected_modes_match_the_exact_limit(chain, mask):
+    """Section 4: infinite covariance on chosen Fourier modes removes them
+    from the data.  The converged iteration equals the exact limit computed
+    on the subspace orthogonal to those modes (and to masked pixels).
+
+    The three-level chain's residual is not usable here: its 1/f term
+    multiplies x by 1e30 on the projected modes, where the pixel-space fields
+    of this reference carry rounding noise; the fields themselves converge,
+    so that chain runs a fixed number of sweeps instead."""
+    p = _projected(_easy_three_term(mask=mask), LOW_MODES)
+    sd = direct.wiener_projected_dense(p)
+    if chain == "augmented":
+        r = oracle.solve(p, oracle.AdaptiveSchedule(lam0=1e3, plateau=1e-3),
+                         settings=oracle.Settings(chain=chain), max_sweeps=40000,
+                         monitor_every=4, rtol=1e-12, full_residual=True)
+        assert r.converged
+    else:
+        r = oracle.solve(p, oracle.FixedSchedule(list(oracle.cooling_ramp(2000, 12000, 1e3))),
+                         settings=oracle.Settings(chain=chain), max_sweeps=12000,
+                         monitor_every=1000)
+    assert np.linalg.norm(r.s - sd) / np.linalg.norm(sd) < 1e-8
+    # the projected modes carry no signal in the result when nothing couples
+    # them to the rest (no mask): the estimate is orthogonal to them
+    if not mask:
+        sk = np.fft.rfft2(r.s)
+        for ky, kx in LOW_MODES:
+            assert abs(sk[ky, kx]) < 1e-8 * np.abs(sk).max()
+
+
+def test_projected_modes_stationary_closed_form():
+    """No mask, uniform white noise: s_k = S / (S + N) d_k with N = inf on the
+    projected modes, i.e. those modes of the estimate are zero."""
+    p = synth.make_stationary_problem(32, 32, 3)
+    p = _projected(p, LOW_MODES)
+    ref = direct.wiener_stationary(p)
+    lams = [1.0]
+    r = oracle.solve(p, oracle.FixedSchedule(lams), settings=oracle.Settings(chain="augmented",
+                     beta=(0.9, 0.9, 1.0)), max_sweeps=1)
+    assert np.linalg.norm(r.s - ref) / np.linalg.norm(ref) < 1e-12
+
+
+def test_projected_mode_errors():
+    p = _easy_three_term()
+    import dataclasses
+    with pytest.raises(oracle.InvalidInput):
+        oracle.setup(dataclasses.replace(p, p_oof=np.full_like(p.p_oof, np.inf)))
+    bad = np.array(p.p_oof)
+    bad[2, 2] = -np.inf
+    with pytest.raises(oracle.InvalidInput):
+        oracle.setup(dataclasses.replace(p, p_oof=bad))
