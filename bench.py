@@ -267,7 +267,8 @@ def main():
             "row_kernel": {"bytes_per_launch": row_bytes(n, n),
                            "mean_launch_us": round(row_ms * 1e3, 2),
                            "achieved": round(row_bytes(n, n) / (row_ms * 1e-3) / 1e9, 1)},
-            "sweep_bytes": cb + row_bytes(n, n)}
+            "sweep_bytes": cb + row_bytes(n, n),
+            "monitor_mean_us": round(1e3 * kms[2] / max(kn[2], 1), 2)}
 
     ttr = None
     if not a.skip_ttr:

@@ -178,12 +178,21 @@ template <> struct plan<1536> { static constexpr int r[4] = {8, 8, 8, 3}; };
 
 constexpr int kE = 16;  // values per thread for power-of-two lengths
 
+// radix plan for a transform spread over E values per thread: the default
+// plan, or (E = 8) radices of at most 8
+template <int N, int E>
+struct plan_for {
+  static constexpr int r0 = plan<N>::r[0], r1 = plan<N>::r[1], r2 = plan<N>::r[2], r3 = plan<N>::r[3];
+};
+template <> struct plan_for<1024, 8> { static constexpr int r0 = 8, r1 = 8, r2 = 4, r3 = 4; };
+template <> struct plan_for<2048, 8> { static constexpr int r0 = 8, r1 = 8, r2 = 8, r3 = 4; };
+template <> struct plan_for<4096, 8> { static constexpr int r0 = 8, r1 = 8, r2 = 8, r3 = 8; };
+
 // One Stockham pass.  reg: the thread's E values; lds: this transform's
 // padded exchange buffer; tw: w_N^j table (forward sign).
-template <class T, int N, int R, int P, bool INV, bool LAST>
+template <class T, int N, int R, int P, bool INV, bool LAST, int E = elems<N>::value>
 __device__ __forceinline__ void stockham_pass(cx<T>* reg, cx<T>* lds, int t,
                                               const cx<T>* __restrict__ tw) {
-  constexpr int E = elems<N>::value;
   constexpr int NT = N / E;
   constexpr int NB = E / R;
   static_assert(E % R == 0, "radix must divide the values per thread");
@@ -224,22 +233,23 @@ __device__ __forceinline__ void stockham_pass(cx<T>* reg, cx<T>* lds, int t,
 // Full transform of length N.  Every thread of the workgroup must call it
 // (it contains barriers); lds must hold padded<N>::value elements per
 // transform and must not be in use by the caller.
-template <class T, int N, bool INV>
+template <class T, int N, bool INV, int E = elems<N>::value>
 __device__ __forceinline__ void fft(cx<T>* reg, cx<T>* lds, int t, const cx<T>* __restrict__ tw) {
-  constexpr int R0 = plan<N>::r[0], R1 = plan<N>::r[1], R2 = plan<N>::r[2], R3 = plan<N>::r[3];
+  using PL = plan_for<N, E>;
+  constexpr int R0 = PL::r0, R1 = PL::r1, R2 = PL::r2, R3 = PL::r3;
   static_assert(R0 * R1 * R2 * R3 == N, "radix plan must multiply to N");
   if constexpr (R2 == 1) {
-    stockham_pass<T, N, R0, 1, INV, false>(reg, lds, t, tw);
-    stockham_pass<T, N, R1, R0, INV, true>(reg, lds, t, tw);
+    stockham_pass<T, N, R0, 1, INV, false, E>(reg, lds, t, tw);
+    stockham_pass<T, N, R1, R0, INV, true, E>(reg, lds, t, tw);
   } else if constexpr (R3 == 1) {
-    stockham_pass<T, N, R0, 1, INV, false>(reg, lds, t, tw);
-    stockham_pass<T, N, R1, R0, INV, false>(reg, lds, t, tw);
-    stockham_pass<T, N, R2, R0 * R1, INV, true>(reg, lds, t, tw);
+    stockham_pass<T, N, R0, 1, INV, false, E>(reg, lds, t, tw);
+    stockham_pass<T, N, R1, R0, INV, false, E>(reg, lds, t, tw);
+    stockham_pass<T, N, R2, R0 * R1, INV, true, E>(reg, lds, t, tw);
   } else {
-    stockham_pass<T, N, R0, 1, INV, false>(reg, lds, t, tw);
-    stockham_pass<T, N, R1, R0, INV, false>(reg, lds, t, tw);
-    stockham_pass<T, N, R2, R0 * R1, INV, false>(reg, lds, t, tw);
-    stockham_pass<T, N, R3, R0 * R1 * R2, INV, true>(reg, lds, t, tw);
+    stockham_pass<T, N, R0, 1, INV, false, E>(reg, lds, t, tw);
+    stockham_pass<T, N, R1, R0, INV, false, E>(reg, lds, t, tw);
+    stockham_pass<T, N, R2, R0 * R1, INV, false, E>(reg, lds, t, tw);
+    stockham_pass<T, N, R3, R0 * R1 * R2, INV, true, E>(reg, lds, t, tw);
   }
 }
 
