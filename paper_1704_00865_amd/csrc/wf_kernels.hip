@@ -270,6 +270,14 @@ constexpr int row_elems() {
   return (sizeof(T) == 4 && (N == 1024 || N == 2048 || N == 4096)) ? 8 : elems<N>::value;
 }
 
+// values per thread of the column kernel's transforms: the default (8 was
+// measured slower at 2048: 37.6 vs 36.5 us; this kernel's per-mode chain
+// keeps more state per value than the row kernel's)
+template <class T, int N>
+constexpr int col_elems() {
+  return elems<N>::value;
+}
+
 // values per thread of the float64 monitor's transforms: 8 at 1024-4096
 // (measured 12% faster than 16 at 2048: 99 vs 113 us per check)
 template <int N>
@@ -476,10 +484,10 @@ template <class T>
 __device__ __forceinline__ cx<T> cconj(cx<T> v) { return cx<T>{v.re, -v.im}; }
 
 template <class T, int NY, int TR, int TC, int MODE, int FK>
-__global__ __launch_bounds__(TC * (NY / elems<NY>::value), (min_waves<T, NY>())) void col_kernel(const SweepArgs<T>* __restrict__ argv, int k_local,
+__global__ __launch_bounds__(TC * (NY / col_elems<T, NY>()), (min_waves<T, NY>())) void col_kernel(const SweepArgs<T>* __restrict__ argv, int k_local,
     cx<T>* __restrict__ spec, double lam_init) {
   const SweepArgs<T>& a = argv[blockIdx.y];  // one map per grid row
-  constexpr int E = elems<NY>::value;
+  constexpr int E = col_elems<T, NY>();
   constexpr int NT = NY / E;
   constexpr int YS = padded<NY>::value;
   constexpr int TRTC = TR * TC;
@@ -572,7 +580,7 @@ __global__ __launch_bounds__(TC * (NY / elems<NY>::value), (min_waves<T, NY>()))
 #pragma unroll
     for (int q = 0; q < E; ++q) reg[q] = lds[c * YS + lpad(t + NT * q)];
     __syncthreads();
-    fft<T, NY, false>(reg, lds + c * YS, t, tw);
+    fft<T, NY, false, E>(reg, lds + c * YS, t, tw);
   }
 
   // packed column (block 0, column 0): split Z = C0 + i CN into the k_x = 0
@@ -697,7 +705,7 @@ __global__ __launch_bounds__(TC * (NY / elems<NY>::value), (min_waves<T, NY>()))
 
   // the inverse transform reuses column 0's LDS region
   __syncthreads();
-  fft<T, NY, true>(reg, lds + c * YS, t, tw);
+  fft<T, NY, true, E>(reg, lds + c * YS, t, tw);
 #pragma unroll
   for (int q = 0; q < E; ++q) lds[c * YS + lpad(t + NT * q)] = reg[q];
   __syncthreads();

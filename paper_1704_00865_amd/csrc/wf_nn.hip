@@ -57,41 +57,68 @@ struct ConvArgs {
   int h, w, cin, cout;
   int flip;            // 1: tap (dy, dx) reads the pixel at (-dy, -dx)
   int relu;
+  int64_t P;           // pixels
 };
 
-// Block: 256 threads, 64 pixels x COT output channels; wave w owns pixels
-// 16w..16w+15 of the block and every column tile.
+// Block: 256 threads, 128 pixels x COT output channels; wave w owns pixels
+// 32w..32w+31 of the block (two 16-row tiles) and every column tile, so each
+// weight fragment feeds two MFMAs.  One tap's weights (COT x cin) are staged
+// in LDS and shared by the four waves.  Pixels past the end (P not a multiple
+// of 128) read a valid pixel and store nothing.
 template <int COT>
 __global__ __launch_bounds__(256) void conv_kernel(ConvArgs a) {
   constexpr int NJ = COT / 16;
+  constexpr int WS = 128 + 8;  // LDS row: up to 128 input channels + pad
+  __shared__ __attribute__((aligned(16))) uint16_t ws[COT * WS];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int r = lane & 15, kq = lane >> 4;
-  const int64_t pw = (int64_t)blockIdx.x * 64 + wave * 16;
+  const int64_t pw = (int64_t)blockIdx.x * 128 + wave * 32;
   const int co0 = blockIdx.y * COT;
   const int hw = a.h * a.w;
-  const int64_t p = pw + r;
-  const int64_t img = p / hw;
-  const int rem = (int)(p - img * hw);
-  const int y = rem / a.w, x = rem - (rem / a.w) * a.w;
-  f32x4 acc[NJ];
+  int64_t img[2];
+  int yy0[2], xx0[2];
 #pragma unroll
-  for (int j = 0; j < NJ; ++j) acc[j] = f32x4{0.f, 0.f, 0.f, 0.f};
+  for (int u = 0; u < 2; ++u) {
+    int64_t p = pw + 16 * u + r;
+    if (p >= a.P) p = a.P - 1;
+    img[u] = p / hw;
+    const int rem = (int)(p - img[u] * hw);
+    yy0[u] = rem / a.w;
+    xx0[u] = rem - yy0[u] * a.w;
+  }
+  f32x4 acc[2][NJ];
+#pragma unroll
+  for (int u = 0; u < 2; ++u)
+#pragma unroll
+    for (int j = 0; j < NJ; ++j) acc[u][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+  const int c8 = a.cin / 8;
   for (int t = 0; t < 9; ++t) {
+    __syncthreads();  // the previous tap's weights have been consumed
+    for (int i = threadIdx.x; i < COT * c8; i += 256) {
+      const int co = i / c8, cc = i - co * c8;
+      *(uint4*)&ws[co * WS + cc * 8] =
+          *(const uint4*)(a.wt + ((int64_t)t * a.cout + co0 + co) * a.cin + cc * 8);
+    }
+    __syncthreads();
     int dy = t / 3 - 1, dx = t % 3 - 1;
     if (a.flip) {
       dy = -dy;
       dx = -dx;
     }
-    const int yy = wrap(y + dy, a.h), xx = wrap(x + dx, a.w);
-    const uint16_t* arow = a.in + (img * hw + (int64_t)yy * a.w + xx) * a.cin + kq * 8;
-    const uint16_t* brow = a.wt + ((int64_t)t * a.cout + co0 + r) * a.cin + kq * 8;
+    const uint16_t* arow[2];
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      const int yy = wrap(yy0[u] + dy, a.h), xx = wrap(xx0[u] + dx, a.w);
+      arow[u] = a.in + (img[u] * hw + (int64_t)yy * a.w + xx) * a.cin + kq * 8;
+    }
     for (int c = 0; c < a.cin; c += 32) {
-      const bf16x8 av = __builtin_bit_cast(bf16x8, *(const uint4*)(arow + c));
+      const bf16x8 a0 = __builtin_bit_cast(bf16x8, *(const uint4*)(arow[0] + c));
+      const bf16x8 a1 = __builtin_bit_cast(bf16x8, *(const uint4*)(arow[1] + c));
 #pragma unroll
       for (int j = 0; j < NJ; ++j) {
-        const bf16x8 bv =
-            __builtin_bit_cast(bf16x8, *(const uint4*)(brow + (int64_t)16 * j * a.cin + c));
-        acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, acc[j], 0, 0, 0);
+        const bf16x8 bv = __builtin_bit_cast(bf16x8, *(const uint4*)&ws[(16 * j + r) * WS + c + kq * 8]);
+        acc[0][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0, bv, acc[0][j], 0, 0, 0);
+        acc[1][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1, bv, acc[1][j], 0, 0, 0);
       }
     }
   }
@@ -101,13 +128,16 @@ __global__ __launch_bounds__(256) void conv_kernel(ConvArgs a) {
     const int co = co0 + 16 * j + r;
     const float bb = a.bias ? a.bias[co] : 0.f;
 #pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const int64_t pp = pw + 4 * kq + v;
-      float val = acc[j][v] + bb;
-      if (a.relu) val = fmaxf(val, 0.f);
-      if (a.out) a.out[pp * a.cout + co] = f2bf(val);
-      if (a.out_f32 && co == 0) a.out_f32[pp] = val;
-    }
+    for (int u = 0; u < 2; ++u)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int64_t pp = pw + 16 * u + 4 * kq + v;
+        if (pp >= a.P) continue;
+        float val = acc[u][j][v] + bb;
+        if (a.relu) val = fmaxf(val, 0.f);
+        if (a.out) a.out[pp * a.cout + co] = f2bf(val);
+        if (a.out_f32 && co == 0) a.out_f32[pp] = val;
+      }
   }
 }
 
@@ -124,69 +154,118 @@ struct WgradArgs {
   int64_t chunk;       // pixels per block, a multiple of 64
 };
 
-// grid (nchunk, 9, (cin/32) * (cout/32)); each block a 32 x 32 tile
+// grid (nchunk, (cin/32) * (cout/32)); each block one 32 x 32 (ci, co) tile
+// of all nine taps over its pixel chunk.  Per 64-pixel slab the output
+// gradient is staged once and the input once per tap (its periodic
+// neighbours), both transposed to [channel][pixel] in LDS so that a lane's 8
+// consecutive pixels are one 16-byte read; wave w owns the 16 x 16 sub-tile
+// (w / 2, w % 2) of every tap.
 __global__ __launch_bounds__(256) void wgrad_kernel(WgradArgs a) {
-  __shared__ __attribute__((aligned(16))) uint16_t xs[32][72];  // [ci][pixel]
-  __shared__ __attribute__((aligned(16))) uint16_t gs[32][72];  // [co][pixel]
-  const int t = blockIdx.y;
+  __shared__ __attribute__((aligned(16))) uint16_t xs[9][32][72];  // [tap][ci][pixel]
+  __shared__ __attribute__((aligned(16))) uint16_t gs[32][72];     // [co][pixel]
   const int ntc = a.cout / 32;
-  const int ci0 = (int)(blockIdx.z / ntc) * 32, co0 = (int)(blockIdx.z % ntc) * 32;
-  const int dy = t / 3 - 1, dx = t % 3 - 1;
+  const int ci0 = (int)(blockIdx.y / ntc) * 32, co0 = (int)(blockIdx.y % ntc) * 32;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int si = (wave >> 1) * 16, sj = (wave & 1) * 16;
   const int sp = threadIdx.x >> 2;         // staged pixel 0..63
   const int sc = (threadIdx.x & 3) * 8;    // staged channel offset
   const int hw = a.h * a.w;
-  f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+  f32x4 acc[9];
+#pragma unroll
+  for (int t = 0; t < 9; ++t) acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
   const int64_t pbeg = (int64_t)blockIdx.x * a.chunk;
   for (int64_t pb = pbeg; pb < pbeg + a.chunk; pb += 64) {
     const int64_t p = pb + sp;
     const int64_t img = p / hw;
     const int rem = (int)(p - img * hw);
     const int y = rem / a.w, x = rem - (rem / a.w) * a.w;
-    const int64_t q = img * hw + (int64_t)wrap(y + dy, a.h) * a.w + wrap(x + dx, a.w);
-    const uint4 xv = *(const uint4*)(a.in + q * a.cin + ci0 + sc);
+    uint4 xv[9];
+#pragma unroll
+    for (int t = 0; t < 9; ++t) {
+      const int dy = t / 3 - 1, dx = t % 3 - 1;
+      const int64_t q = img * hw + (int64_t)wrap(y + dy, a.h) * a.w + wrap(x + dx, a.w);
+      xv[t] = *(const uint4*)(a.in + q * a.cin + ci0 + sc);
+    }
     const uint4 gv = *(const uint4*)(a.g + p * a.cout + co0 + sc);
     __syncthreads();  // the previous slab has been consumed
-    const uint16_t* xe = (const uint16_t*)&xv;
+#pragma unroll
+    for (int t = 0; t < 9; ++t) {
+      const uint16_t* xe = (const uint16_t*)&xv[t];
+#pragma unroll
+      for (int e = 0; e < 8; ++e) xs[t][sc + e][sp] = xe[e];
+    }
     const uint16_t* ge = (const uint16_t*)&gv;
 #pragma unroll
-    for (int e = 0; e < 8; ++e) {
-      xs[sc + e][sp] = xe[e];
-      gs[sc + e][sp] = ge[e];
-    }
+    for (int e = 0; e < 8; ++e) gs[sc + e][sp] = ge[e];
     __syncthreads();
 #pragma unroll
     for (int ks = 0; ks < 64; ks += 32) {
-      const bf16x8 av = __builtin_bit_cast(bf16x8, *(const uint4*)&xs[si + (lane & 15)][ks + 8 * (lane >> 4)]);
       const bf16x8 bv = __builtin_bit_cast(bf16x8, *(const uint4*)&gs[sj + (lane & 15)][ks + 8 * (lane >> 4)]);
-      acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, acc, 0, 0, 0);
+#pragma unroll
+      for (int t = 0; t < 9; ++t) {
+        const bf16x8 av =
+            __builtin_bit_cast(bf16x8, *(const uint4*)&xs[t][si + (lane & 15)][ks + 8 * (lane >> 4)]);
+        acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, acc[t], 0, 0, 0);
+      }
     }
   }
-  float* dst = a.part + (((int64_t)blockIdx.x * 9 + t) * a.cin + ci0 + si) * a.cout + co0 + sj;
 #pragma unroll
-  for (int v = 0; v < 4; ++v) dst[(int64_t)(4 * (lane >> 4) + v) * a.cout + (lane & 15)] = acc[v];
-}
-
-// out[i] = sum_c part[c][i], c in order
-__global__ void chunk_sum_kernel(const float* __restrict__ part, int nchunk, int64_t n,
-                                 float* __restrict__ out) {
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-       i += (int64_t)gridDim.x * blockDim.x) {
-    float s = 0.f;
-    for (int c = 0; c < nchunk; ++c) s += part[(int64_t)c * n + i];
-    out[i] = s;
+  for (int t = 0; t < 9; ++t) {
+    float* dst = a.part + (((int64_t)blockIdx.x * 9 + t) * a.cin + ci0 + si) * a.cout + co0 + sj;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) dst[(int64_t)(4 * (lane >> 4) + v) * a.cout + (lane & 15)] = acc[t][v];
   }
 }
 
-// bias gradient partials: part[chunk][co] = sum over the chunk of g[p][co]
+// out[i] = sum_c part[c][i] in a fixed order.  A block takes 32 consecutive
+// i and 8 groups of chunks (group g sums chunks g, g+8, ...), so that many
+// loads are in flight; the 8 group sums are then added in order.
+__global__ __launch_bounds__(256) void chunk_sum_kernel(const float* __restrict__ part, int nchunk, int64_t n,
+                                                        float* __restrict__ out) {
+  __shared__ float sh[8][32];
+  const int li = threadIdx.x & 31, grp = threadIdx.x >> 5;
+  const int64_t i = (int64_t)blockIdx.x * 32 + li;
+  float s = 0.f;
+  if (i < n)
+    for (int c = grp; c < nchunk; c += 8) s += part[(int64_t)c * n + i];
+  sh[grp][li] = s;
+  __syncthreads();
+  if (grp == 0 && i < n) {
+    float t = 0.f;
+#pragma unroll
+    for (int g = 0; g < 8; ++g) t += sh[g][li];
+    out[i] = t;
+  }
+}
+
+// bias gradient partials: part[chunk][co] = sum over the chunk of g[p][co].
+// A thread reads 8 channels of one pixel per step (16-byte loads, whole
+// pixels per step across the block); the per-thread sums are then added
+// over the block's pixel lanes in LDS.
 __global__ __launch_bounds__(256) void colsum_kernel(const uint16_t* __restrict__ g, int cout,
                                                      int64_t chunk, float* __restrict__ part) {
+  __shared__ float red[256 * 8];
+  const int vpp = cout / 8;            // 16-byte vectors per pixel
+  const int ppi = 256 / vpp;           // pixels per step
+  const int lp = threadIdx.x / vpp, v = threadIdx.x - lp * vpp;
+  float acc[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
   const int64_t pbeg = (int64_t)blockIdx.x * chunk;
+  if (lp < ppi) {
+    for (int64_t p = pbeg + lp; p < pbeg + chunk; p += ppi) {
+      const uint4 u = *(const uint4*)(g + p * cout + 8 * v);
+      const uint16_t* h = (const uint16_t*)&u;
+#pragma unroll
+      for (int e = 0; e < 8; ++e) acc[e] += bf2f(h[e]);
+    }
+  }
+#pragma unroll
+  for (int e = 0; e < 8; ++e) red[threadIdx.x * 8 + e] = acc[e];
+  __syncthreads();
   for (int co = threadIdx.x; co < cout; co += blockDim.x) {
-    float s = 0.f;
-    for (int64_t p = pbeg; p < pbeg + chunk; ++p) s += bf2f(g[p * cout + co]);
-    part[(int64_t)blockIdx.x * cout + co] = s;
+    const int vv = co / 8, e = co - vv * 8;
+    float sum = 0.f;
+    for (int l = 0; l < ppi; ++l) sum += red[(l * vpp + vv) * 8 + e];
+    part[(int64_t)blockIdx.x * cout + co] = sum;
   }
 }
 
@@ -267,15 +346,17 @@ __global__ void ew_kernel(int op, const uint16_t* in, const uint16_t* in2, uint1
 // features, targets, loss, output scaling
 // ---------------------------------------------------------------------------
 
-// sig2[m] = mean of N_pix over the observed pixels of map m (one block per map)
+// per-block partial sums of N_pix and of the observed count over a slice
+// of map blockIdx.x (gridDim.y slices per map): part[m][slice][2]
 template <class T>
 __global__ __launch_bounds__(256) void sigma_kernel(const T* __restrict__ npix,
                                                     const uint8_t* __restrict__ mask, int64_t hw,
-                                                    double* __restrict__ sig2) {
+                                                    double* __restrict__ part) {
   __shared__ double ss[256], sc[256];
   const int64_t base = (int64_t)blockIdx.x * hw;
+  const int64_t len = hw / gridDim.y, beg = (int64_t)blockIdx.y * len;
   double s = 0.0, c = 0.0;
-  for (int64_t i = threadIdx.x; i < hw; i += blockDim.x) {
+  for (int64_t i = beg + threadIdx.x; i < beg + len; i += blockDim.x) {
     const bool o = mask ? mask[base + i] != 0 : true;
     if (o) {
       s += (double)npix[base + i];
@@ -292,7 +373,24 @@ __global__ __launch_bounds__(256) void sigma_kernel(const T* __restrict__ npix,
     }
     __syncthreads();
   }
-  if (threadIdx.x == 0) sig2[blockIdx.x] = sc[0] > 0 ? ss[0] / sc[0] : 1.0;
+  if (threadIdx.x == 0) {
+    double* o = part + 2 * ((int64_t)blockIdx.x * gridDim.y + blockIdx.y);
+    o[0] = ss[0];
+    o[1] = sc[0];
+  }
+}
+
+// sig2[m] = (sum of N_pix) / (observed count) over map m's slices, in order
+__global__ void sigma_final_kernel(const double* __restrict__ part, int slices, int nb,
+                                   double* __restrict__ sig2) {
+  const int m = blockIdx.x * blockDim.x + threadIdx.x;
+  if (m >= nb) return;
+  double s = 0.0, c = 0.0;
+  for (int k = 0; k < slices; ++k) {
+    s += part[2 * ((int64_t)m * slices + k)];
+    c += part[2 * ((int64_t)m * slices + k) + 1];
+  }
+  sig2[m] = c > 0 ? s / c : 1.0;
 }
 
 // rowm[r] = mean over the observed pixels of row r (of all maps) of d, or 0
@@ -388,12 +486,19 @@ __global__ __launch_bounds__(256) void loss_kernel(const float* __restrict__ y, 
   if (threadIdx.x == 0) part[blockIdx.x] = sh[0];
 }
 
-__global__ void loss_final_kernel(const double* __restrict__ part, int n, int64_t P, double* out) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) {
-    double s = 0.0;
-    for (int i = 0; i < n; ++i) s += part[i];
-    *out = s / (double)P;
+// one block of 256 threads: strided partial sums, then a fixed-order tree
+__global__ __launch_bounds__(256) void loss_final_kernel(const double* __restrict__ part, int n, int64_t P,
+                                                         double* out) {
+  __shared__ double sh[256];
+  double s = 0.0;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) s += part[i];
+  sh[threadIdx.x] = s;
+  __syncthreads();
+  for (int k = 128; k > 0; k >>= 1) {
+    if (threadIdx.x < k) sh[threadIdx.x] += sh[threadIdx.x + k];
+    __syncthreads();
   }
+  if (threadIdx.x == 0) *out = sh[0] / (double)P;
 }
 
 template <class T>
@@ -460,11 +565,12 @@ int grid_for(int64_t n, int block = 256, int cap = 8192) {
 
 hipError_t conv(const uint16_t* in, const uint16_t* wt, const float* bias, uint16_t* out, float* out_f32,
                 int64_t P, int h, int w, int cin, int cout, bool flip, bool relu, hipStream_t st) {
-  ConvArgs a{in, wt, bias, out, out_f32, h, w, cin, cout, flip ? 1 : 0, relu ? 1 : 0};
+  ConvArgs a{in, wt, bias, out, out_f32, h, w, cin, cout, flip ? 1 : 0, relu ? 1 : 0, P};
+  const unsigned nb = (unsigned)((P + 127) / 128);
   if (cout % 64 == 0)
-    hipLaunchKernelGGL(conv_kernel<64>, dim3((unsigned)(P / 64), cout / 64), dim3(256), 0, st, a);
+    hipLaunchKernelGGL(conv_kernel<64>, dim3(nb, cout / 64), dim3(256), 0, st, a);
   else
-    hipLaunchKernelGGL(conv_kernel<32>, dim3((unsigned)(P / 64), cout / 32), dim3(256), 0, st, a);
+    hipLaunchKernelGGL(conv_kernel<32>, dim3(nb, cout / 32), dim3(256), 0, st, a);
   return hipGetLastError();
 }
 
@@ -476,22 +582,33 @@ int chunks(int64_t P, int cap) {
     if (slabs % c == 0) return c;
   return 1;
 }
-int wgrad_chunks(int64_t P) { return chunks(P, 64); }
+// capacity of the weight-gradient partial buffer, in floats
+constexpr int64_t kPartFloats = (int64_t)64 * 9 * 128 * 128;
+
+// pixel chunks of the weight gradient: about 1024 blocks in all (more
+// chunks mean more partial sums to add afterwards), within the partial buffer
+int wgrad_chunks(int64_t P, int cin, int cout) {
+  const int tiles = (cin / 32) * (cout / 32);
+  const int64_t want = (1024 + tiles - 1) / tiles;
+  const int64_t cap = kPartFloats / ((int64_t)9 * cin * cout);
+  return chunks(P, (int)std::min(want, cap));
+}
 
 hipError_t wgrad(const uint16_t* in, const uint16_t* g, float* part, float* dw, int64_t P, int h, int w,
                  int cin, int cout, hipStream_t st) {
-  const int nch = wgrad_chunks(P);
+  const int nch = wgrad_chunks(P, cin, cout);
   WgradArgs a{in, g, part, h, w, cin, cout, P / nch};
-  hipLaunchKernelGGL(wgrad_kernel, dim3(nch, 9, (cin / 32) * (cout / 32)), dim3(256), 0, st, a);
+  hipLaunchKernelGGL(wgrad_kernel, dim3(nch, (cin / 32) * (cout / 32)), dim3(256), 0, st, a);
   const int64_t n = (int64_t)9 * cin * cout;
-  hipLaunchKernelGGL(chunk_sum_kernel, dim3(grid_for(n)), dim3(256), 0, st, part, nch, n, dw);
+  hipLaunchKernelGGL(chunk_sum_kernel, dim3((unsigned)((n + 31) / 32)), dim3(256), 0, st, part, nch, n, dw);
   return hipGetLastError();
 }
 
 hipError_t bias_grad(const uint16_t* g, float* part, float* db, int64_t P, int cout, hipStream_t st) {
   const int nch = chunks(P, 256);
-  hipLaunchKernelGGL(colsum_kernel, dim3(nch), dim3(128), 0, st, g, cout, P / nch, part);
-  hipLaunchKernelGGL(chunk_sum_kernel, dim3(1), dim3(128), 0, st, part, nch, (int64_t)cout, db);
+  hipLaunchKernelGGL(colsum_kernel, dim3(nch), dim3(256), 0, st, g, cout, P / nch, part);
+  hipLaunchKernelGGL(chunk_sum_kernel, dim3((unsigned)((cout + 31) / 32)), dim3(256), 0, st, part, nch,
+                     (int64_t)cout, db);
   return hipGetLastError();
 }
 
@@ -635,7 +752,7 @@ wf_status create_net(const wf_nn_shape* s, Net** out) {
   NA(n->tgt, P0 * 4);
   NA(n->sig2, n->nmax * 8);
   NA(n->rowm, (size_t)n->nmax * n->h * 8);
-  NA(n->part, (size_t)64 * 9 * 128 * 128 * 4);
+  NA(n->part, (size_t)kPartFloats * 4);
   NA(n->lpart, 1024 * 8);
   NA(n->loss, 8);
 #undef NA
@@ -696,7 +813,7 @@ wf_status backward(Net* n, int nb, hipStream_t st) {
   const int64_t P0 = (int64_t)nb * n->h * n->w;
   const int nlp = grid_for(P0, 256, 1024);
   hipLaunchKernelGGL(loss_kernel, dim3(nlp), dim3(256), 0, st, n->yf, n->tgt, P0, n->gy, n->lpart);
-  hipLaunchKernelGGL(loss_final_kernel, dim3(1), dim3(64), 0, st, n->lpart, nlp, P0, n->loss);
+  hipLaunchKernelGGL(loss_final_kernel, dim3(1), dim3(256), 0, st, n->lpart, nlp, P0, n->loss);
   NN_TRY(hipGetLastError());
   int k = kLayers - 1;
   {
@@ -758,7 +875,11 @@ template <class T>
 wf_status prepare(Net* n, int nb, const void* d, const void* npix, const uint8_t* mask, const void* s,
                   hipStream_t st) {
   const int64_t hw = (int64_t)n->h * n->w, P0 = nb * hw;
-  hipLaunchKernelGGL(sigma_kernel<T>, dim3(nb), dim3(256), 0, st, (const T*)npix, mask, hw, n->sig2);
+  constexpr int kSlices = 32;  // divides every supported map size
+  hipLaunchKernelGGL(sigma_kernel<T>, dim3(nb, kSlices), dim3(256), 0, st, (const T*)npix, mask, hw,
+                     (double*)n->part);
+  hipLaunchKernelGGL(sigma_final_kernel, dim3((nb + 63) / 64), dim3(64), 0, st, (const double*)n->part,
+                     kSlices, nb, n->sig2);
   hipLaunchKernelGGL(rowmean_kernel<T>, dim3(nb * n->h), dim3(256), 0, st, (const T*)d, mask, n->w, n->rowm);
   hipLaunchKernelGGL(features_kernel<T>, dim3(grid_for(P0)), dim3(256), 0, st, (const T*)d, (const T*)npix,
                      mask, (const T*)s, n->sig2, n->rowm, n->w, hw, P0, n->x, s ? n->tgt : nullptr);
@@ -911,7 +1032,7 @@ wf_status wf_nn_conv3x3(int32_t mode, int32_t nb, int32_t h, int32_t w, int32_t 
   if (mode == 3) {
     if (!g) return WF_EINVAL;
     float* part = nullptr;
-    NN_TRY(hipMalloc((void**)&part, (size_t)wgrad_chunks(P) * 9 * ci * co * 4));
+    NN_TRY(hipMalloc((void**)&part, (size_t)wgrad_chunks(P, ci, co) * 9 * ci * co * 4));
     hipError_t e = wgrad(in, g, part, (float*)out, P, h, w, ci, co, stream);
     if (e == hipSuccess) e = hipStreamSynchronize(stream);
     (void)hipFree(part);

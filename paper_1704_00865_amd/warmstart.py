@@ -110,6 +110,32 @@ def train(net: WarmNet, data: MapSet, *, epochs: int, batch: int, lr: float, see
     return hist
 
 
+def conv_flops_per_step(h: int, w: int, batch: int) -> dict:
+    """Multiply-add work of one training step (forward, input adjoint and
+    weight gradient of every convolution; the first layer's input adjoint is
+    not needed), counting 2 flops per multiply-add.  'executed' uses the
+    stored channel counts (input 4 -> 32, output 1 -> 32), 'useful' the real
+    ones."""
+    from .nn import CHANNELS, layer_shapes
+    shapes = layer_shapes()
+    L = len(CHANNELS)
+    levels = [0, 0]
+    for l in range(1, L):
+        levels += [l, l]
+    for l in range(L - 2, -1, -1):
+        levels += [l, l]
+    levels.append(0)
+    ex = us = 0.0
+    for i, ((ci, co), lev) in enumerate(zip(shapes, levels)):
+        P = batch * (h >> lev) * (w >> lev)
+        cr = 4 if i == 0 else ci
+        orr = 1 if i == len(shapes) - 1 else co
+        passes = 2 if i == 0 else 3
+        ex += passes * 2.0 * 9 * ci * co * P
+        us += passes * 2.0 * 9 * cr * orr * P
+    return {"executed": ex, "useful": us}
+
+
 def predict(net: WarmNet, data: MapSet, batch: int):
     import torch
     out = torch.empty_like(data.d)
@@ -170,6 +196,11 @@ def experiment(train_problems: Sequence, test_problems: Sequence, *, precision: 
            "chain": "augmented", "eval_rtol": eval_rtol, "target_rtol": target_rtol,
            "gen_seconds": round(t_gen, 2), "train_seconds": round(t_train, 2), "train_steps": steps,
            "train_batch": batch, "epochs": epochs, "loss_first_epoch": hist[0],
+           "train_step_ms": round(1e3 * t_train / max(steps, 1), 3),
+           "train_tflops_executed": round(conv_flops_per_step(h, w, batch)["executed"] * steps
+                                          / t_train / 1e12, 2),
+           "train_mfma_frac_bf16": round(conv_flops_per_step(h, w, batch)["executed"] * steps
+                                         / t_train / 2.5e15, 4),
            "loss_last_epoch": hist[-1],
            "pred_rel_error_median": float(np.median(err_pred)),
            "pred_error_energy_in_row_means": frac_rows,
