@@ -44,6 +44,7 @@ from .messenger import (  # noqa: F401
     Settings,
     cooling_ramp,
     diagnostics,
+    diagnostics_of_field,
     init_state,
     inverse_noise_weight,
     joint_objective,

@@ -266,7 +266,19 @@ def diagnostics(st: Setup, x: State, lam: float) -> Diagnostics:
     observed part alone can be tiny while the masked region is still far from
     converged."""
     T0 = lam * st.levels[0].tau
-    xk = rfft2u(x.t[0]) / (st.S_chain.eig + T0)
+    return _diagnostics_of_x(st, rfft2u(x.t[0]) / (st.S_chain.eig + T0))
+
+
+def diagnostics_of_field(st: Setup, u: np.ndarray) -> Diagnostics:
+    """The same residual for a given signal-end field u = S_chain x (for
+    instance a solver's output in field mode 1), with x = S_chain^-1 u formed
+    mode by mode.  Well conditioned for the augmented chain, whose S_chain
+    includes the Fourier-diagonal noise."""
+    return _diagnostics_of_x(st, rfft2u(np.asarray(u, dtype=np.float64)) / st.S_chain.eig)
+
+
+def _diagnostics_of_x(st: Setup, xk: np.ndarray) -> Diagnostics:
+    """Residual of Section 2 from the modes of x = S^-1 s."""
     xs = irfft2u(xk, st.shape)
     # terms diagonal in the 2-D Fourier basis act on x's modes directly (a
     # round trip of x through pixel space would put rounding noise on every

@@ -320,3 +320,29 @@ def test_tilings_give_identical_results(gpu_lib):
             np.testing.assert_array_equal(s, ref[0])
             np.testing.assert_array_equal(trace, ref[1])
     assert n_built >= 2
+
+
+@pytest.mark.parametrize("cfg,prec,bound", [("c2", "f64", 1.0e-6), ("c3", "f64", 1.0e-6),
+                                            ("c2", "f32", 3.0e-5)])
+def test_converged_residual_checked_by_oracle(gpu_lib, cfg, prec, bound):
+    """Full-size zero-start solves (C2 512^2; C3 2048^2 with its mask): the
+    oracle evaluates Section 2's residual of the GPU's converged field itself
+    (augmented chain, field mode 1: u = (S + N_F) x, so x follows without
+    dividing by the signal spectrum).  float64 meets rho <= 1e-6; float32
+    stops at its rounding floor (about 1e-5 here)."""
+    import torch
+    p = synth.named_config(cfg)
+    ny, nx = p.d.shape
+    print(f"converged residual {cfg} {prec}", flush=True)
+    ctx = gpu_lib.Context(ny, nx, prec)
+    sched = gpu_lib.Schedule(lambda0=1e6, rtol=1e-6, max_sweeps=60000 if prec == "f64" else 20000,
+                             monitor_every=16, chain="augmented", chain_field=True)
+    u, rep, _ = ctx.solve(*_tensors(p, prec), schedule=sched)
+    if prec == "f64":
+        assert rep["status"] == "OK"
+    st = oracle.setup(p, oracle.Settings(chain="augmented"))
+    dg = oracle.diagnostics_of_field(st, u.cpu().numpy().astype(np.float64))
+    assert dg.rho <= bound * (1 + 1e-6)
+    if prec == "f64":
+        assert dg.rho == pytest.approx(rep["rho"], rel=1e-6)
+        assert dg.rho_mask == pytest.approx(rep["rho_mask"], rel=1e-6, abs=1e-15)

@@ -207,3 +207,31 @@ def test_training_reduces_the_loss_and_adam_matches(gpu_lib):
     for _ in range(30):
         losses.append(net.train_step(d, npix, mask, tgt, 1e-3))
     assert losses[-1] < 0.5 * losses[0]
+
+
+def test_network_is_translation_equivariant_at_1024(gpu_lib):
+    """At the 1024^2 warm-start size, where the float64 reference would take
+    minutes: the periodic network commutes with translations by multiples of
+    8 pixels (the pooling grid of three levels), and the loss gradient of a
+    translated input and target equals the original one (float32 sums over
+    the pixels in another order)."""
+    import torch
+    from paper_1704_00865_amd import nn
+    print("net 1024 equivariance", flush=True)
+    p = _params(23)
+    net = nn.WarmNet(1024, 1024, batch_max=1)
+    net.set_params(p)
+    _, x = _features(1, 1024, 1024, 24)
+    sh = (64, 200)
+    y = net.forward_features(x)
+    yr = net.forward_features(torch.roll(x, shifts=sh, dims=(1, 2)).contiguous())
+    ref = torch.roll(y, shifts=sh, dims=(1, 2))
+    assert float((yr - ref).abs().max()) <= 1e-5 * float(ref.abs().max())
+    tgt = torch.tensor(np.random.default_rng(25).standard_normal((1, 1024, 1024)),
+                       dtype=torch.float32, device="cuda")
+    g0, l0 = net.gradient_features(x, tgt)
+    g1, l1 = net.gradient_features(torch.roll(x, shifts=sh, dims=(1, 2)).contiguous(),
+                                   torch.roll(tgt, shifts=sh, dims=(1, 2)).contiguous())
+    assert l1 == pytest.approx(l0, rel=1e-5)
+    g0, g1 = g0.double().cpu().numpy(), g1.double().cpu().numpy()
+    assert np.linalg.norm(g1 - g0) <= 1e-3 * np.linalg.norm(g0)

@@ -402,6 +402,8 @@ def test_chain_field_output_and_exact_warm_start(mask):
                      monitor_every=4, rtol=1e-12, full_residual=True, chain_field=True)
     assert r.converged
     assert np.linalg.norm(r.s - ud) / np.linalg.norm(ud) < 1e-9
+    # the residual of the dense field, evaluated from the field alone
+    assert oracle.diagnostics_of_field(st, ud).rho < 1e-9
     w = oracle.solve(p, oracle.FixedSchedule([1.0]), settings=oracle.Settings(chain="augmented"),
                      s_init=ud, max_sweeps=5, monitor_every=1, chain_field=True)
     assert w.trace[0][2] < 1e-9
