@@ -14,7 +14,9 @@ Also printed, on the same JSON line:
                 / its mean duration from HIP events on the solve stream
   time_to_rtol  wall time of a zero-start solve to rho <= 1e-6 on the float64
                 path with the augmented chain (float32 fields settle at a few
-                1e-5 on this map; the three-level chain needs far more sweeps)
+                1e-5 on this map; the three-level chain needs far more sweeps),
+                with the paper's adaptive cooling (lambda^0.7) and with slower
+                cooling (lambda^0.97)
   batch         48 maps of three sizes (16 each of 256^2, 768^2, 1536^2) in
                 one batched solve (shared launches, replayed HIP graph), against
                 the same maps solved one after the other
@@ -274,28 +276,34 @@ def main():
     if not a.skip_ttr:
         # time to rho <= 1e-6: the float32 fields of the iteration settle at a
         # residual of a few 1e-5 on this map, so the float64 path is used,
-        # with the augmented chain (the three-level one needs far more sweeps)
+        # with the augmented chain (the three-level one needs far more sweeps);
+        # once with the adaptive recipe of Section 3.3 (lambda <- lambda^0.7 on
+        # a plateau) and once with slower cooling (lambda <- lambda^0.97 from
+        # 1e4), which reaches the target in far fewer sweeps on this map
         def t64(x):
             return torch.tensor(np.ascontiguousarray(x), dtype=torch.float64, device=dev)
         args64 = (t64(p.d), t64(p.s_k), t64(p.n_pix), t64(p.p_oof), t64(p.p_stripe), args[5])
         ctx64 = wf.Context(n, n, "f64", device=dev)
         out64 = torch.empty((n, n), dtype=torch.float64, device=dev)
-        s2 = wf.Schedule(lambda0=1.0e6, rtol=1e-6, max_sweeps=100000, monitor_every=16,
-                         chain="augmented")
         warm = wf.Schedule(lambda0=1.0e6, rtol=0.0, max_sweeps=64, monitor_every=16,
                            chain="augmented")
         ctx64.solve(*args64, schedule=warm, out=out64)
-        torch.cuda.synchronize()
-        t1 = time.perf_counter()
-        _, r2, _ = ctx64.solve(*args64, schedule=s2, out=out64)
-        torch.cuda.synchronize()
-        t2 = time.perf_counter() - t1
-        ttr = {"chain": "augmented", "dtype": "f64", "rtol": 1e-6, "lambda0": 1.0e6,
-               "status": r2["status"], "sweeps": r2["sweeps"], "seconds": round(t2, 4),
-               "rho": r2["rho"], "rho_mask": r2["rho_mask"],
-               "map_sweeps_per_s": round(r2["sweeps"] / t2, 1)}
-        print(f"[bench] time-to-1e-6 (augmented, f64): {t2:.3f}s, {r2['sweeps']} sweeps, "
-              f"{r2['status']}", file=sys.stderr, flush=True)
+        ttr = {}
+        for name, lam0, shrink in (("tuned", 1.0e4, 0.97), ("paper_recipe", 1.0e6, 0.7)):
+            s2 = wf.Schedule(lambda0=lam0, shrink=shrink, rtol=1e-6, max_sweeps=100000,
+                             monitor_every=16, chain="augmented")
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            _, r2, _ = ctx64.solve(*args64, schedule=s2, out=out64)
+            torch.cuda.synchronize()
+            t2 = time.perf_counter() - t1
+            ttr[name] = {"chain": "augmented", "dtype": "f64", "rtol": 1e-6, "lambda0": lam0,
+                         "shrink": shrink, "plateau": 1e-2, "monitor_every": 16,
+                         "status": r2["status"], "sweeps": r2["sweeps"], "seconds": round(t2, 4),
+                         "rho": r2["rho"], "rho_mask": r2["rho_mask"],
+                         "map_sweeps_per_s": round(r2["sweeps"] / t2, 1)}
+            print(f"[bench] time-to-1e-6 ({name}: augmented, f64, shrink {shrink}): {t2:.3f}s, "
+                  f"{r2['sweeps']} sweeps, {r2['status']}", file=sys.stderr, flush=True)
         ctx64.close()
         del args64, out64
 

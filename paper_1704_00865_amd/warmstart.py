@@ -155,8 +155,9 @@ def rel_error(a, b) -> np.ndarray:
 
 
 def experiment(train_problems: Sequence, test_problems: Sequence, *, precision: str = "f64",
-               target_rtol: float = 1e-5, eval_rtol: float = 1e-6, lam0: float = 1e6,
-               warm_lam0: Sequence[float] = (1e3, 1e2, 10.0), epochs: int = 20, batch: int = 16,
+               target_rtol: float = 1e-5, eval_rtol: float = 1e-6, lam0: float = 1e4,
+               shrink: float = 0.97, warm_lam0: Sequence[float] = (1e3, 1e2, 10.0),
+               epochs: int = 20, batch: int = 16,
                lr: float = 2e-3, seed: int = 0, max_sweeps: int = 200000, log=None) -> dict:
     """Train on solver solutions (chain fields u) of train_problems and
     compare sweeps to rho <= eval_rtol on test_problems from the zero start
@@ -167,8 +168,8 @@ def experiment(train_problems: Sequence, test_problems: Sequence, *, precision: 
     t0 = time.perf_counter()
     tr = stack_problems(train_problems, precision)
     te = stack_problems(test_problems, precision)
-    tsched = Schedule(lambda0=lam0, rtol=target_rtol, max_sweeps=max_sweeps, monitor_every=16,
-                      chain="augmented", chain_field=True)
+    tsched = Schedule(lambda0=lam0, shrink=shrink, rtol=target_rtol, max_sweeps=max_sweeps,
+                      monitor_every=16, chain="augmented", chain_field=True)
     tr.s, rtr = solve_set(train_problems, tr, tsched)
     torch.cuda.synchronize()
     t_gen = time.perf_counter() - t0
@@ -183,8 +184,8 @@ def experiment(train_problems: Sequence, test_problems: Sequence, *, precision: 
     t_train = time.perf_counter() - t1
     steps = epochs * (tr.n // batch)
     # reference solutions of the test maps and the predictions
-    esched = Schedule(lambda0=lam0, rtol=eval_rtol, max_sweeps=max_sweeps, monitor_every=16,
-                      chain="augmented", chain_field=True)
+    esched = Schedule(lambda0=lam0, shrink=shrink, rtol=eval_rtol, max_sweeps=max_sweeps,
+                      monitor_every=16, chain="augmented", chain_field=True)
     s_ref, rzero = solve_set(test_problems, te, esched)
     pred = predict(net, te, max(batch, 8))
     err_pred = rel_error(pred, s_ref)
@@ -204,13 +205,14 @@ def experiment(train_problems: Sequence, test_problems: Sequence, *, precision: 
            "loss_last_epoch": hist[-1],
            "pred_rel_error_median": float(np.median(err_pred)),
            "pred_error_energy_in_row_means": frac_rows,
+           "shrink": shrink,
            "zero": {"lambda0": lam0, "sweeps_mean": float(np.mean([r["sweeps"] for r in rzero])),
                     "converged": int(sum(r["status"] == "OK" for r in rzero)),
                     "rel_error_start_median": float(np.median(err_zero))},
            "warm": []}
     for l0 in warm_lam0:
-        sch = Schedule(lambda0=l0, rtol=eval_rtol, max_sweeps=max_sweeps, monitor_every=16,
-                       chain="augmented", chain_field=True)
+        sch = Schedule(lambda0=l0, shrink=shrink, rtol=eval_rtol, max_sweeps=max_sweeps,
+                       monitor_every=16, chain="augmented", chain_field=True)
         _, rw = solve_set(test_problems, te, sch, s_init=pred)
         res["warm"].append({"lambda0": l0,
                             "sweeps_mean": float(np.mean([r["sweeps"] for r in rw])),
@@ -219,8 +221,8 @@ def experiment(train_problems: Sequence, test_problems: Sequence, *, precision: 
             log(f"warm lambda0={l0:g}: network {res['warm'][-1]['sweeps_mean']:.0f} sweeps, "
                 f"zero start {res['zero']['sweeps_mean']:.0f}")
     # reference: the converged field itself as the start, at lambda = 1
-    sch = Schedule(lambda0=1.0, rtol=eval_rtol, max_sweeps=max_sweeps, monitor_every=16,
-                   chain="augmented", chain_field=True)
+    sch = Schedule(lambda0=1.0, shrink=shrink, rtol=eval_rtol, max_sweeps=max_sweeps,
+                   monitor_every=16, chain="augmented", chain_field=True)
     _, rx = solve_set(test_problems, te, sch, s_init=s_ref)
     res["exact_start"] = {"lambda0": 1.0, "sweeps_mean": float(np.mean([r["sweeps"] for r in rx]))}
     best = min(res["warm"], key=lambda r: (-r["converged"], r["sweeps_mean"]))
