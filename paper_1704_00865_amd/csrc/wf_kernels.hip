@@ -262,12 +262,12 @@ constexpr bool lds_twiddles() {
 }
 
 // values per thread of the row kernel's transforms: 8 for the float32
-// lengths 1024-4096 (twice the threads of 16 values, so twice the waves to
-// hide the row kernel's memory latency; measured 6% faster at 2048), else
-// the default
+// lengths 1024 and 2048 (twice the threads of 16 values, so twice the waves
+// to hide the row kernel's memory latency; measured 6% faster at 2048), else
+// the default (at 4096, 8 values would make 1024-thread blocks that spill)
 template <class T, int N>
 constexpr int row_elems() {
-  return (sizeof(T) == 4 && (N == 1024 || N == 2048 || N == 4096)) ? 8 : elems<N>::value;
+  return (sizeof(T) == 4 && (N == 1024 || N == 2048)) ? 8 : elems<N>::value;
 }
 
 // values per thread of the column kernel's transforms: the default (8 was
@@ -526,8 +526,9 @@ __global__ __launch_bounds__(TC * (NY / col_elems<T, NY>()), (min_waves<T, NY>()
   const cx<T>* tw = LTW ? (const cx<T>*)twl : twg;
 
   // per-mode state and coefficients of this column, loaded in batches of 8
-  // (float32) or 4 (float64) modes
-  constexpr int HB = sizeof(T) == 8 ? 4 : 8;
+  // modes, or 4 where the registers are scarce (float64, 24 values per
+  // thread, or 4096 points; 8 spilled there)
+  constexpr int HB = (sizeof(T) == 8 || E == 24 || NY >= 4096) ? 4 : 8;
   constexpr bool hasA = FK != FK_NONE;
   constexpr bool hasB = FK == FK_ARRAY_STRIPE;
   constexpr bool needNb = FK == FK_ARRAY || FK == FK_ARRAY_STRIPE;
