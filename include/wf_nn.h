@@ -93,7 +93,10 @@ wf_status wf_nn_gradient_features(void* net, int32_t n, const float* x, const fl
  *   mode 2  out = adjoint in the input: g [P][co] -> out bf16 [P][ci]
  *   mode 3  out = weight gradient: sum_p in[p + tap]^T g[p], float32 [3][3][ci][co]
  * w is bf16 [3][3][ci][co] (modes 0-2); b float32 [co] or NULL; for mode 3
- * `w` is unused and `g` is the output gradient.  ci, co multiples of 32. */
+ * `w` is unused and `g` is the output gradient.  ci, co multiples of 32 up to
+ * 128; n*H*W a multiple of 64.  Allocates and frees a temporary (modes 0, 1
+ * and 3) and synchronises the stream: a building block for tests, not for
+ * the training loop. */
 wf_status wf_nn_conv3x3(int32_t mode, int32_t n, int32_t h, int32_t w, int32_t ci, int32_t co,
                         const uint16_t* in, const uint16_t* wt, const float* b,
                         const uint16_t* g, void* out, hipStream_t stream);
