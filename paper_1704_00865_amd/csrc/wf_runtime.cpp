@@ -505,6 +505,22 @@ wf_status enqueue_chunk(std::vector<ShapeClass<T>>& cls, const std::vector<MapRu
   return WF_OK;
 }
 
+// One class's K sweeps and its monitor, on one stream (a branch of the batch
+// graph: the classes of a batch are independent until the controller).
+template <class T>
+wf_status enqueue_class(ShapeClass<T>& cl, const std::vector<MapRun<T>>& runs, int K, hipStream_t st) {
+  const SweepArgs<T>& a0 = runs[cl.maps[0]].a;
+  const MonArgs<T>& m0 = runs[cl.maps[0]].m;
+  const int n = (int)cl.maps.size();
+  for (int k = 0; k < K; ++k) {
+    WF_TRY(launch_row<T>(cl.tile, ROW_SWEEP, a0, cl.argv, n, k, nullptr, nullptr, st));
+    WF_TRY(launch_col<T>(cl.tile, COL_SWEEP, a0, cl.argv, n, k, nullptr, 0.0, st));
+  }
+  WF_TRY(launch_mon_col<T>(m0, cl.margv, n, MON_RESIDUAL, st));
+  WF_TRY(launch_mon_row<T>(m0, cl.margv, n, MON_RESIDUAL, st));
+  return WF_OK;
+}
+
 void fill_report(wf_report* rep, const DevSched& fin, const Chain& ch, const double* pix) {
   std::memset(rep, 0, sizeof(*rep));
   rep->status = fin.status;
@@ -619,8 +635,14 @@ wf_status solve_batch_t(Ctx** ctxs, int n, const wf_inputs* ins, const wf_schedu
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   hipEvent_t ev_in = nullptr, ev_ring[kRing] = {};
+  std::vector<hipStream_t> bs;     // one capture branch per shape class
+  std::vector<hipEvent_t> bev;     // fork event + one join event per class
   wf_status ret = WF_OK;
   auto cleanup = [&]() {
+    for (auto& e : bev)
+      if (e) (void)hipEventDestroy(e);
+    for (auto& b : bs)
+      if (b) (void)hipStreamDestroy(b);
     if (exec) (void)hipGraphExecDestroy(exec);
     if (graph) (void)hipGraphDestroy(graph);
     if (cs) (void)hipStreamDestroy(cs);
@@ -701,8 +723,24 @@ wf_status solve_batch_t(Ctx** ctxs, int n, const wf_inputs* ins, const wf_schedu
   const int K = s->monitor_every;
   int n_chunks = 0;
   for (auto& r : runs) n_chunks = std::max(n_chunks, r.n_chunks);
+  // the chunk's classes run as parallel branches of the graph (small maps
+  // fill the GPU beside large ones), joined before the controller
+  const int nc = (int)cls.size();
+  bs.assign(nc, nullptr);
+  bev.assign(nc + 1, nullptr);
+  for (int c = 0; c < nc; ++c) BT(hipStreamCreateWithFlags(&bs[c], hipStreamNonBlocking));
+  for (int c = 0; c <= nc; ++c) BT(hipEventCreateWithFlags(&bev[c], hipEventDisableTiming));
   BT(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
-  wf_status es = enqueue_chunk<T>(cls, runs, dctrl, n, K, nullptr, cs);
+  wf_status es = WF_OK;
+  hipError_t fe = hipEventRecord(bev[nc], cs);
+  for (int c = 0; c < nc && fe == hipSuccess && es == WF_OK; ++c) {
+    fe = hipStreamWaitEvent(bs[c], bev[nc], 0);
+    if (fe == hipSuccess) es = enqueue_class<T>(cls[c], runs, K, bs[c]);
+    if (fe == hipSuccess && es == WF_OK) fe = hipEventRecord(bev[c], bs[c]);
+    if (fe == hipSuccess && es == WF_OK) fe = hipStreamWaitEvent(cs, bev[c], 0);
+  }
+  if (fe == hipSuccess && es == WF_OK) fe = launch_controller(dctrl, n, cs);
+  if (fe != hipSuccess && es == WF_OK) es = from_hip(fe);
   hipError_t ce = hipStreamEndCapture(cs, &graph);
   if (es != WF_OK) {
     cleanup();
