@@ -121,7 +121,7 @@ def bench_batch(wf, oracle, synth, torch, dev, a):
     as the single-map workload.  Compared with solving the same maps one
     after the other."""
     print("[bench] generating the 48-map batch", file=sys.stderr, flush=True)
-    probs = synth.survey_batch()
+    probs = synth.uneven_batch()
 
     def t(x):
         return None if x is None else torch.tensor(np.ascontiguousarray(x),

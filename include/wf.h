@@ -139,8 +139,9 @@ void wf_ctx_destroy(void* ctx);
 void wf_schedule_default(wf_schedule* sch);
 
 /* Solve.  s_init: DEVICE [ny*nx] warm start (every messenger and data-like
- * field starts at s_init, Section 2 notes the start is not critical), or NULL
- * for the zero start of Section 2.  s_out: DEVICE [ny*nx].  rep: HOST, may be
+ * field starts at s_init; by Section 2 the start does not change the
+ * solution), or NULL for the zero start of Section 2.  s_out: DEVICE
+ * [ny*nx].  rep: HOST, may be
  * NULL.  trace: HOST [5 * ceil(max_sweeps / monitor_every)] rows of
  * (sweep index, lambda, rho, dd2, rho_mask), or NULL. */
 wf_status wf_solve(void* ctx, const wf_inputs* in, const wf_schedule* sch,
@@ -150,8 +151,9 @@ wf_status wf_solve(void* ctx, const wf_inputs* in, const wf_schedule* sch,
 /* Largest batch wf_solve_batch accepts. */
 #define WF_BATCH_MAX 1024
 
-/* Solve n independent maps with one schedule (Section 2 iteration; the
- * survey setting of Section 5 filters many maps of a few shapes).  Maps of
+/* Solve n independent maps with one schedule (the Section 2 iteration for
+ * each; batching is not from the paper: a sky survey yields many maps of a
+ * few shapes).  Maps of
  * equal shape and chain kind share every kernel launch (one grid row per
  * map); one chunk of monitor_every sweeps of every map plus their monitors
  * is recorded once as a HIP graph and replayed, and each map keeps its own

@@ -2,9 +2,9 @@
  * that predicts the Wiener solution from (d, N_pix, mask), trained and run on
  * the GPU with bfloat16 matrix-core convolutions and float32 accumulation.
  *
- * The paper's iteration may start from any field (Section 2: the start is not
- * critical to reach the solution); this library supplies a start.  The
- * network is not from the paper.
+ * The paper's iteration may start from any field (Section 2: the start does
+ * not change the solution); this library supplies a start.  The network is
+ * not from the paper.
  *
  * Network (fixed architecture, 15 convolutions, periodic 3x3 kernels):
  *   levels l = 0..3 with channels C = {32, 64, 96, 128}, each level at half

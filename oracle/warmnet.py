@@ -1,7 +1,7 @@
 """Convolutional warm-start predictor, plain float64 NumPy (test infrastructure).
 
 The messenger iteration may start from any field (Section 2 notes that the
-start is not critical); this module is the reference for a small network that
+start does not change the solution); this module is the reference for a small network that
 predicts the Wiener solution from the data so that the iteration can start
 from the prediction.  The network is not from the paper.  Everything here is
 written for readability: circular 3x3 convolutions as sums of shifted copies,

@@ -14,5 +14,5 @@ from .maps import (  # noqa: F401
     make_stationary_problem,
     named_config,
     pixel_size_rad,
-    survey_batch,
+    uneven_batch,
 )

@@ -222,7 +222,7 @@ def named_config(name: str) -> Problem:
     raise KeyError(name)
 
 
-def survey_batch(sizes=(256, 768, 1536), per_size: int = 16, base_seed: int = 4000):
+def uneven_batch(sizes=(256, 768, 1536), per_size: int = 16, base_seed: int = 4000):
     """Batch of independent maps of uneven size (default 16 each of 256^2,
     768^2 and 1536^2, 48 maps, 48.2 M pixels).  Map i (in order of the sizes)
     uses seed base_seed + i and a noise level L_i drawn uniformly in

@@ -146,7 +146,7 @@ def test_batch_errors(gpu_lib):
     torch.cuda.synchronize()
 
 
-def test_survey_batch_shapes(gpu_lib):
+def test_uneven_batch_shapes(gpu_lib):
     """48 maps of three sizes (16 each of 256^2, 768^2, 1536^2) in one batch:
     every map equals its single solve bit for bit (sampled), and a 256^2 map
     matches the oracle."""
@@ -154,7 +154,7 @@ def test_survey_batch_shapes(gpu_lib):
     probs = [synth.make_problem(n, n, 700 + i, mask_frac=0.05) for i, n in enumerate(sizes)]
     lams = list(oracle.cooling_ramp(8, 16, 300.0))
     sched = gpu_lib.Schedule(lambdas=lams, rtol=0.0, max_sweeps=len(lams), monitor_every=8)
-    print("survey batch 48 maps", flush=True)
+    print("uneven batch 48 maps", flush=True)
     outs, reps = _batch(gpu_lib, probs, "f32", sched)
     assert all(r["sweeps"] == len(lams) for r in reps)
     for i in (0, 15, 16, 31, 32, 47):
