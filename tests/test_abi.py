@@ -84,3 +84,28 @@ def test_ctypes_layout_matches_c_structs(tmp_path):
                    ctypes.sizeof(wf._Inputs), ctypes.sizeof(wf._Shape),
                    wf._Schedule.chain.offset, wf._Report.kernel_ms.offset,
                    ctypes.sizeof(nn._NNShape)]
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libwf.so not built")
+def test_host_side_argument_checks():
+    """Entry points reject bad arguments before any device call."""
+    import paper_1704_00865_amd as wf
+    import paper_1704_00865_amd.nn as nn
+    lib = nn._lib()
+    h = ctypes.c_void_p()
+    for shape, code in (((100, 128, 1, 0), -6), ((32, 64, 1, 0), -6), ((64, 64, 0, 0), -1),
+                        ((64, 64, 1, 7), -1), ((4096, 64, 1, 0), -6)):
+        st = lib.wf_nn_create(ctypes.byref(nn._NNShape(*shape)), ctypes.byref(h))
+        assert st == code, (shape, st)
+        assert not h.value
+    assert lib.wf_nn_create(None, ctypes.byref(h)) == -1
+    # unsupported solver shapes and precisions
+    s = wf._Shape(100, 128, 0)
+    assert lib.wf_ctx_create(ctypes.byref(s), ctypes.byref(h)) == -6
+    s = wf._Shape(64, 64, 5)
+    assert lib.wf_ctx_create(ctypes.byref(s), ctypes.byref(h)) == -1
+    # null handles
+    assert lib.wf_solve(None, None, None, None, None, None, None, None) == -1
+    assert lib.wf_solve_batch(None, 0, None, None, None, None, None, None) == -1
+    assert lib.wf_nn_predict(None, 1, None, None, None, None, None) == -1
+    assert lib.wf_nn_conv3x3(9, 1, 8, 8, 32, 32, None, None, None, None, None, None) == -1
