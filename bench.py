@@ -339,7 +339,23 @@ def main():
             if time.perf_counter() - tc > a.cpu_seconds:
                 break
         tcpu = time.perf_counter() - tc
+        # the same sweeps on one thread, for a per-core figure (a few seconds)
+        oracle.bases.set_workers(1)
+        t1c = time.perf_counter()
+        k1 = 0
+        while time.perf_counter() - t1c < min(5.0, a.cpu_seconds / 3):
+            oracle.sweep(st, x, 1.0)
+            k1 += 1
+        t1c = time.perf_counter() - t1c
+        oracle.bases.set_workers(cores)
+        model = ""
+        try:
+            with open("/proc/cpuinfo") as fh:
+                model = next((l.split(":", 1)[1].strip() for l in fh if l.startswith("model name")), "")
+        except OSError:
+            pass
         cpu = {"value": round(k / tcpu, 4), "unit": "map-sweeps/s", "cores": cores,
+               "one_core_value": round(k1 / t1c, 4), "host_cpu": model,
                "kind": "oracle",
                "sample": f"{k} float64 sweeps of the same {n}x{n} three-level problem "
                          f"({tcpu:.1f} s, scipy.fft workers={cores}); setup and monitor excluded"}
