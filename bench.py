@@ -23,6 +23,8 @@ Also printed, on the same JSON line:
   warm_start    the learned warm start: a network trained in the run on solver
                 solutions of 256^2 maps, then sweeps to rho <= 1e-6 on held-out
                 maps from the zero start and from the network's prediction
+  section4      the two further uses Section 4 names (inverse-noise weighting
+                with S = alpha I; projected Fourier modes), float64, to 1e-6
   cpu_baseline  the float64 CPU oracle on a bounded sample of sweeps
 """
 
@@ -87,6 +89,7 @@ def _args():
     ap.add_argument("--skip-ttr", action="store_true")
     ap.add_argument("--skip-batch", action="store_true")
     ap.add_argument("--skip-warm", action="store_true")
+    ap.add_argument("--skip-sec4", action="store_true")
     ap.add_argument("--warm-size", type=int, default=256)
     ap.add_argument("--warm-train", type=int, default=512)
     ap.add_argument("--warm-test", type=int, default=16)
@@ -169,6 +172,45 @@ def bench_batch(wf, oracle, synth, torch, dev, a):
             "algorithmic_GBps": round(gbs, 1), "frac_of_hbm_peak": round(gbs / HBM_PEAK_GBS, 4),
             "note": "sweep kernels only in the algorithmic bytes (monitor every "
                     f"{a.monitor_every} sweeps is extra work inside the time)"}
+
+
+def bench_section4(wf, torch, dev, p, n):
+    """The two uses of the solver that Section 4 names, on the same 2048^2
+    map, float64 augmented chain to rho <= 1e-6: the approximate
+    inverse-noise weighting N^-1 d with S = alpha I (alpha a thousandth of the
+    smallest white variance), and the Wiener filter with the lowest Fourier
+    modes (|k_x|, |k_y| <= 2) projected out by an infinite 1/f variance."""
+    def t64(x):
+        return None if x is None else torch.tensor(np.ascontiguousarray(x), dtype=torch.float64,
+                                                   device=dev)
+    mask = torch.tensor(p.mask, dtype=torch.uint8, device=dev)
+    ctx = wf.Context(n, n, "f64", device=dev)
+    sch = wf.Schedule(lambda0=1.0e4, shrink=0.97, rtol=1e-6, max_sweeps=100000,
+                      monitor_every=16, chain="augmented")
+    out = {}
+    alpha = 1e-3 * float(np.min(p.n_pix[p.mask != 0]))
+    args = (t64(p.d), t64(p.n_pix), t64(p.p_oof), t64(p.p_stripe), mask)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, r, _ = ctx.inverse_noise_weight(*args, alpha=alpha, schedule=sch)
+    torch.cuda.synchronize()
+    out["inverse_noise"] = {"alpha": alpha, "status": r["status"], "sweeps": r["sweeps"],
+                            "seconds": round(time.perf_counter() - t0, 4), "rho": r["rho"]}
+    po = np.array(p.p_oof, dtype=np.float64)
+    for ky in (0, 1, 2, n - 2, n - 1):
+        po[ky, :3] = np.inf
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, r, _ = ctx.solve(t64(p.d), t64(p.s_k), t64(p.n_pix), t64(po), t64(p.p_stripe), mask,
+                        schedule=sch)
+    torch.cuda.synchronize()
+    out["projected_modes"] = {"modes": "|k_x| <= 2 and |k_y| <= 2", "status": r["status"],
+                              "sweeps": r["sweeps"],
+                              "seconds": round(time.perf_counter() - t0, 4), "rho": r["rho"]}
+    ctx.close()
+    print(f"[bench] section 4: inverse-noise {out['inverse_noise']['seconds']} s, "
+          f"projected modes {out['projected_modes']['seconds']} s", file=sys.stderr, flush=True)
+    return out
 
 
 def main():
@@ -307,6 +349,10 @@ def main():
         ctx64.close()
         del args64, out64
 
+    sec4 = None
+    if not a.skip_sec4:
+        sec4 = bench_section4(wf, torch, dev, p, n)
+
     batch = None
     if not a.skip_batch:
         batch = bench_batch(wf, oracle, synth, torch, dev, a)
@@ -385,6 +431,7 @@ def main():
         "time_to_rtol": ttr,
         "batch": batch,
         "warm_start": warm,
+        "section4": sec4,
         "cpu_baseline": cpu,
         "final_rho": rep["rho"] if rep else None,
     }
