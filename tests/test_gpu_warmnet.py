@@ -235,3 +235,29 @@ def test_network_is_translation_equivariant_at_1024(gpu_lib):
     assert l1 == pytest.approx(l0, rel=1e-5)
     g0, g1 = g0.double().cpu().numpy(), g1.double().cpu().numpy()
     assert np.linalg.norm(g1 - g0) <= 1e-3 * np.linalg.norm(g0)
+
+
+def test_warm_start_pipeline(gpu_lib):
+    """End to end on small maps: solver targets (chain field), a short
+    training run, then the solve from the prediction reaches the same
+    solution as the zero start; the prediction beats the zero prediction, and
+    the exact field as a start converges at once."""
+    import torch
+    import synth
+    from paper_1704_00865_amd import warmstart
+    trp = [synth.make_problem(64, 64, 300 + i, mask_frac=0.1) for i in range(48)]
+    tep = [synth.make_problem(64, 64, 400 + i, mask_frac=0.1) for i in range(4)]
+    print("warm start pipeline", flush=True)
+    res = warmstart.experiment(trp, tep, epochs=6, batch=8, lr=2e-3, warm_lam0=(1e3,),
+                               eval_rtol=1e-6, target_rtol=1e-6)
+    assert res["zero"]["converged"] == 4 and res["warm"][0]["converged"] == 4
+    assert res["pred_rel_error_median"] < 0.9
+    assert res["loss_last_epoch"] < res["loss_first_epoch"]
+    assert res["exact_start"]["sweeps_mean"] <= 32
+    # same solution from either start
+    te = warmstart.stack_problems(tep)
+    sched = gpu_lib.Schedule(lambda0=1e4, shrink=0.97, rtol=1e-9, max_sweeps=200000,
+                             monitor_every=16, chain="augmented", chain_field=True)
+    s0, _ = warmstart.solve_set(tep, te, sched)
+    s1, _ = warmstart.solve_set(tep, te, sched, s_init=torch.zeros_like(te.d) + 1.0)
+    assert float(warmstart.rel_error(s1, s0).max()) < 1e-6
