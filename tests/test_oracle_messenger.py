@@ -490,3 +490,19 @@ def test_projected_mode_errors():
     bad[2, 2] = -np.inf
     with pytest.raises(oracle.InvalidInput):
         oracle.setup(dataclasses.replace(p, p_oof=bad))
+
+
+def test_projected_dense_limit_matches_closed_form():
+    """The exact projected-mode limit (dense, on the orthogonal subspace)
+    equals the Fourier closed form with zero gain on the projected modes when
+    the noise is stationary (no mask, uniform white noise), and equals the
+    plain dense Wiener filter when nothing is projected."""
+    p = synth.make_stationary_problem(16, 16, 4, pix_arcmin=8.0)
+    q = _projected(p, [(0, 0), (1, 0), (15, 0), (0, 1)])
+    a = direct.wiener_projected_dense(q)
+    b = direct.wiener_stationary(q)
+    assert np.linalg.norm(a - b) / np.linalg.norm(b) < 1e-10
+    r = _easy_three_term(mask=True)
+    c = direct.wiener_projected_dense(r)
+    d = direct.wiener_dense(r)
+    assert np.linalg.norm(c - d) / np.linalg.norm(d) < 1e-10
