@@ -312,6 +312,9 @@ def main():
                            "mean_launch_us": round(row_ms * 1e3, 2),
                            "achieved": round(row_bytes(n, n) / (row_ms * 1e-3) / 1e9, 1)},
             "sweep_bytes": cb + row_bytes(n, n),
+            "sweep_achieved": round((cb + row_bytes(n, n)) / ((col_ms + row_ms) * 1e-3) / 1e9, 1),
+            "sweep_frac": round((cb + row_bytes(n, n)) / ((col_ms + row_ms) * 1e-3) / 1e9
+                                / HBM_PEAK_GBS, 4),
             "monitor_mean_us": round(1e3 * kms[2] / max(kn[2], 1), 2)}
 
     ttr = None
