@@ -303,7 +303,11 @@ __global__ __launch_bounds__((RW / 2) * (NX / row_elems<T, NX>()), (min_waves<T,
   constexpr int KPC = NX / 2;                 // packed half width
   constexpr int SUB = RW * KPC;               // complex values of this block's rows
   constexpr int XS = padded<NX>::value;
-  constexpr int LDSN = (SUB > RP * XS) ? SUB : RP * XS;
+  // the band is staged row-major with a padded row stride, so that reading
+  // one row's consecutive k_x and writing a tile's rows are free of LDS bank
+  // conflicts (the tile order of the transit buffer is not)
+  constexpr int RS = KPC + 4;
+  constexpr int LDSN = (RW * RS > RP * XS) ? RW * RS : RP * XS;
   constexpr int EPC = 16 / (2 * (int)sizeof(T));  // complex values per 16 bytes
   __shared__ __align__(16) cx<T> lds[LDSN];
   constexpr bool LTW = lds_twiddles<T, NX>();
@@ -334,7 +338,8 @@ __global__ __launch_bounds__((RW / 2) * (NX / row_elems<T, NX>()), (min_waves<T,
   if constexpr (MODE == ROW_SWEEP || MODE == ROW_C2R) {
     for (int e = tid * EPC; e < SUB; e += blockDim.x * EPC) {
       const int g = e / (RW * TC), w = e - g * (RW * TC);
-      copy16(&lds[e], &gband[g * (TR * TC) + w]);
+      const int rr = w / TC, cc = w - rr * TC;
+      copy16(&lds[rr * RS + g * TC + cc], &gband[g * (TR * TC) + w]);
     }
     __syncthreads();
     // Z = A + i B for the row pair; A, B Hermitian in k_x; slot 0 packs
@@ -345,8 +350,8 @@ __global__ __launch_bounds__((RW / 2) * (NX / row_elems<T, NX>()), (min_waves<T,
       const bool hi = k > NX / 2;
       const int kx = hi ? NX - k : k;
       const int ks = (kx == NX / 2) ? 0 : kx;
-      const int li = (ks / TC) * (RW * TC) + (2 * p) * TC + (ks % TC);
-      cx<T> A = lds[li], Bv = lds[li + TC];
+      const int li = (2 * p) * RS + ks;
+      cx<T> A = lds[li], Bv = lds[li + RS];
       if (kx == 0) {
         A.im = (T)0;
         Bv.im = (T)0;
