@@ -188,9 +188,50 @@ template <> struct plan_for<1024, 8> { static constexpr int r0 = 8, r1 = 8, r2 =
 template <> struct plan_for<2048, 8> { static constexpr int r0 = 8, r1 = 8, r2 = 8, r3 = 4; };
 template <> struct plan_for<4096, 8> { static constexpr int r0 = 8, r1 = 8, r2 = 8, r3 = 8; };
 
+// Twiddle tables.  The natural table holds w_N^j (forward sign) at j; pass
+// (span P, radix R) reads it at j = m k N/(P R), so that the lanes of one read
+// fall on a few LDS banks.  The pass-major table of a radix plan holds, for
+// every pass after the first in order, w_N^{m k N/(P R)} at
+// off + (m - 1) P + k (m = 1..R-1, k = 0..P-1): lanes with consecutive k read
+// consecutive entries.  It has N - R0 entries (the spans grow by the factor R,
+// so the passes' counts (R - 1) P add up to N - R0).
+template <int N, int E>
+struct twp_offsets {
+  using PL = plan_for<N, E>;
+  static constexpr int p1 = PL::r0, p2 = p1 * PL::r1, p3 = p2 * PL::r2;
+  static constexpr int o2 = 0;                             // pass 2 (span p1)
+  static constexpr int o3 = o2 + (PL::r1 - 1) * p1;        // pass 3 (span p2)
+  static constexpr int o4 = o3 + (PL::r2 - 1) * p2;        // pass 4 (span p3)
+  static constexpr int size = N - p1;
+};
+
+// Fill the pass-major table twp (LDS, twp_offsets::size entries) from the
+// natural table tw; threads tid of nthr share the work.
+template <class T, int N, int E>
+__device__ __forceinline__ void stage_twiddles(cx<T>* twp, const cx<T>* __restrict__ tw, int tid,
+                                               int nthr) {
+  using PL = plan_for<N, E>;
+  using O = twp_offsets<N, E>;
+  for (int e = tid; e < O::size; e += nthr) {
+    int j;
+    if (e < O::o3) {
+      const int o = e - O::o2, m = 1 + o / O::p1, k = o - (m - 1) * O::p1;
+      j = m * k * (N / (O::p1 * PL::r1));
+    } else if (e < O::o4) {
+      const int o = e - O::o3, m = 1 + o / O::p2, k = o - (m - 1) * O::p2;
+      j = m * k * (N / (O::p2 * PL::r2));
+    } else {
+      const int o = e - O::o4, m = 1 + o / O::p3, k = o - (m - 1) * O::p3;
+      j = m * k * (N / (O::p3 * PL::r3));
+    }
+    twp[e] = tw[j];
+  }
+}
+
 // One Stockham pass.  reg: the thread's E values; lds: this transform's
-// padded exchange buffer; tw: w_N^j table (forward sign).
-template <class T, int N, int R, int P, bool INV, bool LAST, int E = elems<N>::value>
+// padded exchange buffer; tw: the natural twiddle table (OFF < 0) or the
+// pass-major one, whose entries for this pass start at OFF.
+template <class T, int N, int R, int P, bool INV, bool LAST, int E = elems<N>::value, int OFF = -1>
 __device__ __forceinline__ void stockham_pass(cx<T>* reg, cx<T>* lds, int t,
                                               const cx<T>* __restrict__ tw) {
   constexpr int NT = N / E;
@@ -207,7 +248,7 @@ __device__ __forceinline__ void stockham_pass(cx<T>* reg, cx<T>* lds, int t,
       constexpr int STEP = N / (P * R);
 #pragma unroll
       for (int m = 1; m < R; ++m) {
-        cx<T> w = tw[m * k * STEP];
+        cx<T> w = OFF >= 0 ? tw[OFF + (m - 1) * P + k] : tw[m * k * STEP];
         if (INV) w.im = -w.im;
         u[m] = cmul(u[m], w);
       }
@@ -232,24 +273,27 @@ __device__ __forceinline__ void stockham_pass(cx<T>* reg, cx<T>* lds, int t,
 
 // Full transform of length N.  Every thread of the workgroup must call it
 // (it contains barriers); lds must hold padded<N>::value elements per
-// transform and must not be in use by the caller.
-template <class T, int N, bool INV, int E = elems<N>::value>
+// transform and must not be in use by the caller.  tw is the natural
+// twiddle table, or the pass-major one of plan_for<N, E> when TWP.
+template <class T, int N, bool INV, int E = elems<N>::value, bool TWP = false>
 __device__ __forceinline__ void fft(cx<T>* reg, cx<T>* lds, int t, const cx<T>* __restrict__ tw) {
   using PL = plan_for<N, E>;
+  using O = twp_offsets<N, E>;
   constexpr int R0 = PL::r0, R1 = PL::r1, R2 = PL::r2, R3 = PL::r3;
   static_assert(R0 * R1 * R2 * R3 == N, "radix plan must multiply to N");
+  constexpr int F2 = TWP ? O::o2 : -1, F3 = TWP ? O::o3 : -1, F4 = TWP ? O::o4 : -1;
   if constexpr (R2 == 1) {
     stockham_pass<T, N, R0, 1, INV, false, E>(reg, lds, t, tw);
-    stockham_pass<T, N, R1, R0, INV, true, E>(reg, lds, t, tw);
+    stockham_pass<T, N, R1, R0, INV, true, E, F2>(reg, lds, t, tw);
   } else if constexpr (R3 == 1) {
     stockham_pass<T, N, R0, 1, INV, false, E>(reg, lds, t, tw);
-    stockham_pass<T, N, R1, R0, INV, false, E>(reg, lds, t, tw);
-    stockham_pass<T, N, R2, R0 * R1, INV, true, E>(reg, lds, t, tw);
+    stockham_pass<T, N, R1, R0, INV, false, E, F2>(reg, lds, t, tw);
+    stockham_pass<T, N, R2, R0 * R1, INV, true, E, F3>(reg, lds, t, tw);
   } else {
     stockham_pass<T, N, R0, 1, INV, false, E>(reg, lds, t, tw);
-    stockham_pass<T, N, R1, R0, INV, false, E>(reg, lds, t, tw);
-    stockham_pass<T, N, R2, R0 * R1, INV, false, E>(reg, lds, t, tw);
-    stockham_pass<T, N, R3, R0 * R1 * R2, INV, true, E>(reg, lds, t, tw);
+    stockham_pass<T, N, R1, R0, INV, false, E, F2>(reg, lds, t, tw);
+    stockham_pass<T, N, R2, R0 * R1, INV, false, E, F3>(reg, lds, t, tw);
+    stockham_pass<T, N, R3, R0 * R1 * R2, INV, true, E, F4>(reg, lds, t, tw);
   }
 }
 

@@ -254,8 +254,9 @@ __device__ __forceinline__ void copy16(cx<T>* dst, const cx<T>* src) {
 // ---------------------------------------------------------------------------
 // row kernel: inverse row FFT -> white-level update -> forward row FFT
 // ---------------------------------------------------------------------------
-// twiddle table staged in LDS when it is small (float32 up to 2048 points);
-// larger tables are read through the L1/L2 caches
+// twiddle table staged in LDS, in the pass-major order of the kernel's radix
+// plan, when it is small (float32 up to 2048 points); larger tables are read
+// in natural order through the L1/L2 caches
 template <class T, int N>
 constexpr bool lds_twiddles() {
   return N * 2 * (int)sizeof(T) <= 16384;
@@ -331,7 +332,7 @@ __global__ __launch_bounds__((RW / 2) * (NX / row_elems<T, NX>()), (min_waves<T,
   const int ya = y0 + 2 * p;
   cx<T> reg[E];
   if constexpr (LTW) {
-    for (int j = tid; j < NX; j += blockDim.x) twl[j] = twg[j];
+    stage_twiddles<T, NX, E>(twl, twg, tid, blockDim.x);
   }
   const cx<T>* tw = LTW ? (const cx<T>*)twl : twg;
 
@@ -366,7 +367,7 @@ __global__ __launch_bounds__((RW / 2) * (NX / row_elems<T, NX>()), (min_waves<T,
       reg[q] = cx<T>{A.re - Bv.im, A.im + Bv.re};
     }
     __syncthreads();
-    fft<T, NX, true, E>(reg, lds + p * XS, t, tw);
+    fft<T, NX, true, E, LTW>(reg, lds + p * XS, t, tw);
     const T sc = (T)a.scale;
     if constexpr (MODE == ROW_C2R) {
 #pragma unroll
@@ -407,7 +408,7 @@ __global__ __launch_bounds__((RW / 2) * (NX / row_elems<T, NX>()), (min_waves<T,
     }
     if constexpr (LTW) __syncthreads();
   }
-  fft<T, NX, false, E>(reg, lds + p * XS, t, tw);
+  fft<T, NX, false, E, LTW>(reg, lds + p * XS, t, tw);
 #pragma unroll
   for (int q = 0; q < E; ++q) lds[p * XS + lpad(t + NT * q)] = reg[q];
   __syncthreads();
@@ -526,7 +527,7 @@ __global__ __launch_bounds__(TC * (NY / col_elems<T, NY>()), (min_waves<T, NY>()
   const cx<T>* twg = (const cx<T>*)a.twy;
   cx<T> reg[E];
   if constexpr (LTW) {
-    for (int j = tid; j < NY; j += blockDim.x) twl[j] = twg[j];
+    stage_twiddles<T, NY, E>(twl, twg, tid, blockDim.x);
   }
   const cx<T>* tw = LTW ? (const cx<T>*)twl : twg;
 
@@ -586,7 +587,7 @@ __global__ __launch_bounds__(TC * (NY / col_elems<T, NY>()), (min_waves<T, NY>()
 #pragma unroll
     for (int q = 0; q < E; ++q) reg[q] = lds[c * YS + lpad(t + NT * q)];
     __syncthreads();
-    fft<T, NY, false, E>(reg, lds + c * YS, t, tw);
+    fft<T, NY, false, E, LTW>(reg, lds + c * YS, t, tw);
   }
 
   // packed column (block 0, column 0): split Z = C0 + i CN into the k_x = 0
@@ -711,7 +712,7 @@ __global__ __launch_bounds__(TC * (NY / col_elems<T, NY>()), (min_waves<T, NY>()
 
   // the inverse transform reuses column 0's LDS region
   __syncthreads();
-  fft<T, NY, true, E>(reg, lds + c * YS, t, tw);
+  fft<T, NY, true, E, LTW>(reg, lds + c * YS, t, tw);
 #pragma unroll
   for (int q = 0; q < E; ++q) lds[c * YS + lpad(t + NT * q)] = reg[q];
   __syncthreads();
