@@ -146,19 +146,30 @@ __device__ __forceinline__ void dft(cx<T>* u) {
   else if constexpr (R == 16) dft16<T, INV>(u);
 }
 
-// LDS index with one pad slot per 16 elements (breaks the stride-16 bank
-// conflicts of the first pass's scattered stores)
-__device__ __forceinline__ int lpad(int j) { return j + (j >> 4); }
-template <int N>
-struct padded {
-  static constexpr int value = N + N / 16;
-};
-
 // complex values held by each thread: 16 for powers of two, 24 for lengths
 // with a factor 3 (so that both radix 8 and radix 3 divide it)
 template <int N>
 struct elems {
   static constexpr int value = (N % 3 == 0) ? 24 : 16;
+};
+
+// Index map of one transform's LDS exchange buffer (N complex values, E per
+// thread).  With 8-byte values and at least one wave per transform, the low
+// five bits of the index are XORed with those of 5 (j >> 5): each aligned run
+// of 32 values is permuted within itself, so natural-order accesses stay free
+// of bank conflicts, while the strided stores of the passes spread over the
+// 64 banks.  Buffers of one block are then N + 16 values apart (32 banks), so
+// a wave that touches two of them does not collide with itself.  Otherwise
+// (16-byte values, or several transforms per wave) one pad value per 16.
+template <class T, int N, int E>
+struct ldsmap {
+  static constexpr bool swz = sizeof(T) == 4 && N / E >= 64;
+  static_assert(!swz || N % 32 == 0, "the swizzle permutes aligned runs of 32");
+  static constexpr int size = swz ? N + 16 : N + N / 16;
+  __device__ __forceinline__ static int at(int j) {
+    if constexpr (swz) return j ^ ((5 * (j >> 5)) & 31);
+    else return j + (j >> 4);
+  }
 };
 
 // radix plan R0 * R1 * R2 * R3 = N (1 = no pass); a radix-3 pass comes last
@@ -236,6 +247,7 @@ __device__ __forceinline__ void stockham_pass(cx<T>* reg, cx<T>* lds, int t,
                                               const cx<T>* __restrict__ tw) {
   constexpr int NT = N / E;
   constexpr int NB = E / R;
+  using LM = ldsmap<T, N, E>;
   static_assert(E % R == 0, "radix must divide the values per thread");
 #pragma unroll
   for (int b = 0; b < NB; ++b) {
@@ -260,19 +272,19 @@ __device__ __forceinline__ void stockham_pass(cx<T>* reg, cx<T>* lds, int t,
     } else {
       const int j = (i - k) * R + k;
 #pragma unroll
-      for (int m = 0; m < R; ++m) lds[lpad(j + m * P)] = u[m];
+      for (int m = 0; m < R; ++m) lds[LM::at(j + m * P)] = u[m];
     }
   }
   if constexpr (!LAST) {
     __syncthreads();
 #pragma unroll
-    for (int q = 0; q < E; ++q) reg[q] = lds[lpad(t + NT * q)];
+    for (int q = 0; q < E; ++q) reg[q] = lds[LM::at(t + NT * q)];
     __syncthreads();
   }
 }
 
 // Full transform of length N.  Every thread of the workgroup must call it
-// (it contains barriers); lds must hold padded<N>::value elements per
+// (it contains barriers); lds must hold ldsmap<T, N, E>::size elements per
 // transform and must not be in use by the caller.  tw is the natural
 // twiddle table, or the pass-major one of plan_for<N, E> when TWP.
 template <class T, int N, bool INV, int E = elems<N>::value, bool TWP = false>

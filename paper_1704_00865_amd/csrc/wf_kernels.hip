@@ -303,11 +303,13 @@ __global__ __launch_bounds__((RW / 2) * (NX / row_elems<T, NX>()), (min_waves<T,
   constexpr int RP = RW / 2;
   constexpr int KPC = NX / 2;                 // packed half width
   constexpr int SUB = RW * KPC;               // complex values of this block's rows
-  constexpr int XS = padded<NX>::value;
-  // the band is staged row-major with a padded row stride, so that reading
-  // one row's consecutive k_x and writing a tile's rows are free of LDS bank
-  // conflicts (the tile order of the transit buffer is not)
-  constexpr int RS = KPC + 4;
+  using LM = ldsmap<T, NX, E>;  // exchange-buffer index map
+  constexpr int XS = LM::size;
+  // the band is staged row-major with a padded row stride (rows 16 banks
+  // apart), so that reading one row's consecutive k_x and writing a tile's
+  // rows are free of LDS bank conflicts (the tile order of the transit buffer
+  // is not)
+  constexpr int RS = KPC + 8;
   constexpr int LDSN = (RW * RS > RP * XS) ? RW * RS : RP * XS;
   constexpr int EPC = 16 / (2 * (int)sizeof(T));  // complex values per 16 bytes
   __shared__ __align__(16) cx<T> lds[LDSN];
@@ -410,7 +412,7 @@ __global__ __launch_bounds__((RW / 2) * (NX / row_elems<T, NX>()), (min_waves<T,
   }
   fft<T, NX, false, E, LTW>(reg, lds + p * XS, t, tw);
 #pragma unroll
-  for (int q = 0; q < E; ++q) lds[p * XS + lpad(t + NT * q)] = reg[q];
+  for (int q = 0; q < E; ++q) lds[p * XS + LM::at(t + NT * q)] = reg[q];
   __syncthreads();
   // split Z into the two rows' spectra; write this block's rows, tile order
   for (int e = tid * EPC; e < SUB; e += blockDim.x * EPC) {
@@ -423,10 +425,10 @@ __global__ __launch_bounds__((RW / 2) * (NX / row_elems<T, NX>()), (min_waves<T,
       const int kx = g * TC + c;
       const cx<T>* Z = lds + (rr >> 1) * XS;
       if (kx == 0) {
-        const cx<T> z0 = Z[0], zn = Z[lpad(NX / 2)];
+        const cx<T> z0 = Z[LM::at(0)], zn = Z[LM::at(NX / 2)];
         v[u] = (rr & 1) ? cx<T>{z0.im, zn.im} : cx<T>{z0.re, zn.re};
       } else {
-        const cx<T> zk = Z[lpad(kx)], zm = Z[lpad(NX - kx)];
+        const cx<T> zk = Z[LM::at(kx)], zm = Z[LM::at(NX - kx)];
         v[u] = (rr & 1) ? cx<T>{(zk.im + zm.im) * (T)0.5, (zm.re - zk.re) * (T)0.5}
                         : cx<T>{(zk.re + zm.re) * (T)0.5, (zk.im - zm.im) * (T)0.5};
       }
@@ -495,7 +497,8 @@ __global__ __launch_bounds__(TC * (NY / col_elems<T, NY>()), (min_waves<T, NY>()
   const SweepArgs<T>& a = argv[blockIdx.y];  // one map per grid row
   constexpr int E = col_elems<T, NY>();
   constexpr int NT = NY / E;
-  constexpr int YS = padded<NY>::value;
+  using LM = ldsmap<T, NY, E>;  // exchange-buffer index map
+  constexpr int YS = LM::size;
   constexpr int TRTC = TR * TC;
   constexpr int EPC = 16 / (2 * (int)sizeof(T));
   __shared__ __align__(16) cx<T> lds[TC * YS];
@@ -580,12 +583,12 @@ __global__ __launch_bounds__(TC * (NY / col_elems<T, NY>()), (min_waves<T, NY>()
 #pragma unroll
       for (int u = 0; u < EPC; ++u) {
         const int r = (w + u) / TC, cc = (w + u) - r * TC;
-        lds[cc * YS + lpad(yb * TR + r)] = v[u];
+        lds[cc * YS + LM::at(yb * TR + r)] = v[u];
       }
     }
     __syncthreads();
 #pragma unroll
-    for (int q = 0; q < E; ++q) reg[q] = lds[c * YS + lpad(t + NT * q)];
+    for (int q = 0; q < E; ++q) reg[q] = lds[c * YS + LM::at(t + NT * q)];
     __syncthreads();
     fft<T, NY, false, E, LTW>(reg, lds + c * YS, t, tw);
   }
@@ -598,7 +601,7 @@ __global__ __launch_bounds__(TC * (NY / col_elems<T, NY>()), (min_waves<T, NY>()
     if (g == 0) {
       if (packed) {
 #pragma unroll
-        for (int q = 0; q < E; ++q) lds[lpad(t + NT * q)] = reg[q];
+        for (int q = 0; q < E; ++q) lds[LM::at(t + NT * q)] = reg[q];
       }
       __syncthreads();
       cx<T> cnv[E];
@@ -606,7 +609,7 @@ __global__ __launch_bounds__(TC * (NY / col_elems<T, NY>()), (min_waves<T, NY>()
 #pragma unroll
         for (int q = 0; q < E; ++q) {
           const int ky = t + NT * q;
-          const cx<T> zk = reg[q], zm = lds[lpad(ky == 0 ? 0 : NY - ky)];
+          const cx<T> zk = reg[q], zm = lds[LM::at(ky == 0 ? 0 : NY - ky)];
           reg[q] = cx<T>{(zk.re + zm.re) * (T)0.5, (zk.im - zm.im) * (T)0.5};
           cnv[q] = cx<T>{(zk.im + zm.im) * (T)0.5, (zm.re - zk.re) * (T)0.5};
         }
@@ -614,7 +617,7 @@ __global__ __launch_bounds__(TC * (NY / col_elems<T, NY>()), (min_waves<T, NY>()
       __syncthreads();
       if (packed) {
 #pragma unroll
-        for (int q = 0; q < E; ++q) cnl[lpad(t + NT * q)] = cnv[q];
+        for (int q = 0; q < E; ++q) cnl[LM::at(t + NT * q)] = cnv[q];
       }
     }
   }
@@ -624,7 +627,7 @@ __global__ __launch_bounds__(TC * (NY / col_elems<T, NY>()), (min_waves<T, NY>()
     for (int q = 0; q < E; ++q) {
       const size_t row = (size_t)(t + NT * q) * nh;
       spec[row + kxc] = reg[q];
-      if (packed) spec[row + kxn] = cnl[lpad(t + NT * q)];
+      if (packed) spec[row + kxn] = cnl[LM::at(t + NT * q)];
     }
     return;
   }
@@ -645,7 +648,7 @@ __global__ __launch_bounds__(TC * (NY / col_elems<T, NY>()), (min_waves<T, NY>()
       for (int q = 0; q < E; ++q) {
         const int ky = t + NT * q;
         const size_t idx = (size_t)kxn * NY + ky;
-        const int li = lpad(ky);
+        const int li = LM::at(ky);
         cnl[li] = chain_mode<T, FK>(a, k, kxn, ky, idx, cnl[li], a.sc[idx],
                              needNb ? a.nbA[idx] : (T)0, needP ? a.pst[ky] : (T)0,
                              hasA ? ((cx<T>*)a.tA)[idx] : z, hasB ? ((cx<T>*)a.dA)[idx] : z,
@@ -667,7 +670,7 @@ __global__ __launch_bounds__(TC * (NY / col_elems<T, NY>()), (min_waves<T, NY>()
     if (packed) {
 #pragma unroll
       for (int q = 0; q < E; ++q) {
-        const cx<T> cv = cnl[lpad(t + NT * q)];
+        const cx<T> cv = cnl[LM::at(t + NT * q)];
         reg[q] = cx<T>{reg[q].re - cv.im, reg[q].im + cv.re};
       }
     }
@@ -691,7 +694,7 @@ __global__ __launch_bounds__(TC * (NY / col_elems<T, NY>()), (min_waves<T, NY>()
         if (h == 1 && !packed) break;
         const int kx = h == 0 ? kxc : kxn;
         const size_t idx = (size_t)kx * NY + ky;
-        cx<T> v = h == 0 ? reg[q] : cnl[lpad(ky)];
+        cx<T> v = h == 0 ? reg[q] : cnl[LM::at(ky)];
         if (a.fk == FK_NONE) {
           if (!a.warm_chain) {
             const T s = a.sc[idx];
@@ -714,7 +717,7 @@ __global__ __launch_bounds__(TC * (NY / col_elems<T, NY>()), (min_waves<T, NY>()
   __syncthreads();
   fft<T, NY, true, E, LTW>(reg, lds + c * YS, t, tw);
 #pragma unroll
-  for (int q = 0; q < E; ++q) lds[c * YS + lpad(t + NT * q)] = reg[q];
+  for (int q = 0; q < E; ++q) lds[c * YS + LM::at(t + NT * q)] = reg[q];
   __syncthreads();
   for (int e = tid * EPC; e < TC * NY; e += blockDim.x * EPC) {
     const int yb = e / TRTC, w = e - yb * TRTC;
@@ -722,7 +725,7 @@ __global__ __launch_bounds__(TC * (NY / col_elems<T, NY>()), (min_waves<T, NY>()
 #pragma unroll
     for (int u = 0; u < EPC; ++u) {
       const int r = (w + u) / TC, cc = (w + u) - r * TC;
-      v[u] = lds[cc * YS + lpad(yb * TR + r)];
+      v[u] = lds[cc * YS + LM::at(yb * TR + r)];
     }
     copy16(&gB[((size_t)yb * G + g) * TRTC + w], v);
   }
@@ -746,7 +749,8 @@ __global__ __launch_bounds__(kTCM * (NY / mon_elems<NY>())) void mon_col_kernel(
   const MonArgs<T>& m = argv[blockIdx.y];
   constexpr int E = mon_elems<NY>();
   constexpr int NT = NY / E;
-  constexpr int YS = padded<NY>::value;
+  using LM = ldsmap<double, NY, E>;  // exchange-buffer index map
+  constexpr int YS = LM::size;
   constexpr int TRTC = kTRM * kTCM;
   __shared__ cx<double> lds[kTCM * YS];
   // residual: lambda of the chunk's last sweep; output: of the last sweep run
@@ -782,12 +786,12 @@ __global__ __launch_bounds__(kTCM * (NY / mon_elems<NY>())) void mon_col_kernel(
     cx<double>* dst = field == 0 ? m.Mx : m.My;
     fft<double, NY, true, E>(reg, lds + c * YS, t, m.twy);
 #pragma unroll
-    for (int q = 0; q < E; ++q) lds[c * YS + lpad(t + NT * q)] = reg[q];
+    for (int q = 0; q < E; ++q) lds[c * YS + LM::at(t + NT * q)] = reg[q];
     __syncthreads();
     for (int e = tid; e < kTCM * NY; e += blockDim.x) {
       const int yb = e / TRTC, w = e - yb * TRTC;
       const int r = w / kTCM, cc = w - r * kTCM;
-      dst[((size_t)yb * G + g) * TRTC + w] = lds[cc * YS + lpad(yb * kTRM + r)];
+      dst[((size_t)yb * G + g) * TRTC + w] = lds[cc * YS + LM::at(yb * kTRM + r)];
     }
     __syncthreads();
   }
@@ -801,7 +805,8 @@ __global__ __launch_bounds__(kTRM * (NX / mon_elems<NX>())) void mon_row_kernel(
   constexpr int NT = NX / E;
   constexpr int KPm = KP<NX, kTCM>::value;
   constexpr int BANDm = kTRM * KPm;
-  constexpr int XS = padded<NX>::value;
+  using LM = ldsmap<double, NX, E>;  // exchange-buffer index map
+  constexpr int XS = LM::size;
   constexpr int LDSN = (2 * BANDm > kTRM * XS) ? 2 * BANDm : kTRM * XS;
   __shared__ cx<double> lds[LDSN];
   __shared__ double sh[32];
