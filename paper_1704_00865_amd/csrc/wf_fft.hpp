@@ -160,12 +160,14 @@ struct elems {
 // of bank conflicts, while the strided stores of the passes spread over the
 // 64 banks.  Buffers of one block are then N + 16 values apart (32 banks), so
 // a wave that touches two of them does not collide with itself.  Otherwise
-// (16-byte values, or several transforms per wave) one pad value per 16.
+// (16-byte values, or several transforms per wave) one pad value per 16, and
+// buffers N + N/16 + 8 values apart, so that neighbouring buffers start on
+// different banks.
 template <class T, int N, int E>
 struct ldsmap {
   static constexpr bool swz = sizeof(T) == 4 && N / E >= 64;
   static_assert(!swz || N % 32 == 0, "the swizzle permutes aligned runs of 32");
-  static constexpr int size = swz ? N + 16 : N + N / 16;
+  static constexpr int size = swz ? N + 16 : N + N / 16 + 8;
   __device__ __forceinline__ static int at(int j) {
     if constexpr (swz) return j ^ ((5 * (j >> 5)) & 31);
     else return j + (j >> 4);

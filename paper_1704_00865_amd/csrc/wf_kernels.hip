@@ -805,9 +805,13 @@ __global__ __launch_bounds__(kTRM * (NX / mon_elems<NX>())) void mon_row_kernel(
   constexpr int NT = NX / E;
   constexpr int KPm = KP<NX, kTCM>::value;
   constexpr int BANDm = kTRM * KPm;
+  // the two bands are staged row-major, X rows then Y rows, with a row stride
+  // of 8 mod 16 values (rows 32 banks apart): reading a row's consecutive k_x
+  // and writing a tile's rows are then free of bank conflicts
+  constexpr int RSm = KPm + ((8 - KPm % 16) + 16) % 16;
   using LM = ldsmap<double, NX, E>;  // exchange-buffer index map
   constexpr int XS = LM::size;
-  constexpr int LDSN = (2 * BANDm > kTRM * XS) ? 2 * BANDm : kTRM * XS;
+  constexpr int LDSN = (2 * kTRM * RSm > kTRM * XS) ? 2 * kTRM * RSm : kTRM * XS;
   __shared__ cx<double> lds[LDSN];
   __shared__ double sh[32];
   double lamv = 0.0;
@@ -816,8 +820,11 @@ __global__ __launch_bounds__(kTRM * (NX / mon_elems<NX>())) void mon_row_kernel(
   const cx<double>* gx = m.Mx + (size_t)band * BANDm;
   const cx<double>* gy = m.My + (size_t)band * BANDm;
   for (int e = tid; e < BANDm; e += blockDim.x) {
-    lds[e] = gx[e];
-    lds[BANDm + e] = gy[e];
+    // tile order [kx / kTCM][row][kx % kTCM]
+    const int g = e / (kTRM * kTCM), w = e - g * (kTRM * kTCM);
+    const int rr = w / kTCM, kx = g * kTCM + (w - rr * kTCM);
+    lds[rr * RSm + kx] = gx[e];
+    lds[(kTRM + rr) * RSm + kx] = gy[e];
   }
   __syncthreads();
   const int r = tid / NT, t = tid - r * NT;
@@ -827,8 +834,8 @@ __global__ __launch_bounds__(kTRM * (NX / mon_elems<NX>())) void mon_row_kernel(
     const int k = t + NT * q;
     const bool hi = k > NX / 2;
     const int kx = hi ? NX - k : k;
-    const int li = (kx / kTCM) * (kTRM * kTCM) + r * kTCM + (kx % kTCM);
-    cx<double> X = lds[li], Y = lds[BANDm + li];
+    const int li = r * RSm + kx;
+    cx<double> X = lds[li], Y = lds[kTRM * RSm + li];
     if (kx == 0 || kx == NX / 2) {
       X.im = 0.0;
       Y.im = 0.0;
