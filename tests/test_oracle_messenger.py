@@ -5,13 +5,19 @@ the exact minimiser of a dense joint quadratic, a dense Cholesky solve, a
 Fourier closed form, the chi^2 gradient, or an invariant of the method.
 """
 
+import dataclasses
+import json
+import os
+
 import numpy as np
 import pytest
 
 import oracle
 import synth
-from oracle import bases, direct
+from oracle import bases, direct, messenger
 from oracle.messenger import State
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
 
 
 # --------------------------------------------------------------------------
@@ -324,6 +330,53 @@ def test_more_noise_in_fourier_level_converges_faster():
         assert r.converged
         sweeps[frac] = r.sweeps
     assert sweeps[0.99] < sweeps[0.5]
+
+
+def _chi2_uniform(p, s, sigma2):
+    """chi^2(s) = |d - s|^2 / sigma^2 + s^T S^-1 s for uniform white noise,
+    with the unitary transform's half-plane weights (nx even)."""
+    nx = p.d.shape[1]
+    sk = np.fft.rfft2(s, norm="ortho")
+    w = np.ones_like(p.s_k)
+    w[:, 1:nx // 2] = 2.0
+    return float(np.sum((p.d - s) ** 2) / sigma2 + np.sum(w * np.abs(sk) ** 2 / p.s_k))
+
+
+def test_section_3_1_iteration_counts_match_the_paper():
+    """Section 3.1 prints how many iterations (no cooling) the method needs
+    before chi^2 is within one part in 1e3 of its converged value, for
+    uniform white noise with 99% or 50% of its power in the harmonic term
+    N_0: 4 and 75.  The oracle (default tau fractions) on a 64^2 map with a
+    red signal spectrum needs exactly 4 for the 99% split; the 50% count
+    depends on the signal spectrum (the paper's is a beam-smoothed CMB
+    spectrum on a HEALPix N_side = 64 sphere), so it is held to a factor
+    of two of the printed value."""
+    gold = json.load(open(os.path.join(GOLDEN, "sec3_1_uniform_noise.json")))
+    n = 64
+    p0 = synth.make_problem(n, n, 7, oof_level=None, stripe_rms=None, white_contrast=0.0,
+                            mask_frac=0.0)
+    sigma2 = float(p0.n_pix[0, 0])
+    dk = np.fft.rfft2(p0.d, norm="ortho")
+    s_star = np.fft.irfft2(p0.s_k / (p0.s_k + sigma2) * dk, s=(n, n), norm="ortho")
+    c_star = _chi2_uniform(p0, s_star, sigma2)
+    counts = []
+    for frac in gold["fraction_in_N0"]:
+        p = dataclasses.replace(p0, p_oof=np.full_like(p0.s_k, frac * sigma2),
+                                n_pix=np.full_like(p0.n_pix, (1 - frac) * sigma2))
+        st = oracle.setup(p)
+        x = oracle.init_state(st, 1.0)
+        k = 0
+        while k < 1000:
+            oracle.sweep(st, x, 1.0)
+            k += 1
+            s = messenger.final_signal(st, x, 1.0)
+            if abs(_chi2_uniform(p, s, sigma2) - c_star) / c_star < 1e-3:
+                break
+        counts.append(k)
+    k99, k50 = counts
+    g99, g50 = gold["iterations"]
+    assert k99 == g99
+    assert g50 / 2 <= k50 <= 2 * g50
 
 
 def test_convergence_is_exponential_at_unit_lambda():
