@@ -316,6 +316,22 @@ def main():
             "sweep_frac": round((cb + row_bytes(n, n)) / ((col_ms + row_ms) * 1e-3) / 1e9
                                 / HBM_PEAK_GBS, 4),
             "monitor_mean_us": round(1e3 * kms[2] / max(kn[2], 1), 2)}
+    # context for the fractions above: a plain device-to-device copy of the
+    # column kernel's byte count (half read, half written), timed the same way
+    cp_n = cb // 8
+    src = torch.ones(cp_n, dtype=torch.float32, device=dev)
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(20):
+        dst.copy_(src)
+    e1.record()
+    torch.cuda.synchronize()
+    cp_us = 1e3 * e0.elapsed_time(e1) / 20
+    roof["copy_reference"] = {"bytes": 2 * cp_n * 4, "mean_us": round(cp_us, 2),
+                              "GBps": round(2 * cp_n * 4 / (cp_us * 1e-6) / 1e9, 1)}
+    del src, dst
 
     ttr = None
     if not a.skip_ttr:

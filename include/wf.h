@@ -85,6 +85,11 @@ typedef struct {         /* DEVICE pointers, caller-owned, read-only during the 
   const void* p_stripe;  /* [ny] stripe 1-D mode variance >= 0, or NULL (absent)  */
   const uint8_t* mask;   /* [ny*nx] 1 observed / 0 masked, or NULL (all observed) */
 } wf_inputs;
+/* The spectra are covariances of real fields, so they are even in k: on the
+ * real columns k_x = 0 and k_x = nx/2, s_k and p_oof must hold the same value
+ * at k_y and ny - k_y, and p_stripe[k_y] must equal p_stripe[ny - k_y]
+ * (exactly; WF_EINVAL otherwise).  The sweep updates those two columns on
+ * k_y <= ny/2 and takes the other half by conjugation. */
 
 typedef struct {         /* HOST struct */
   int32_t kind;          /* wf_sched_kind                                               */

@@ -115,7 +115,8 @@ __global__ __launch_bounds__(256) void stats_pixels_kernel(const T* __restrict__
 }
 
 // per block: min S, min P_1/f, min over modes of (P_1/f + nx P_st on k_x = 0),
-//            #bad S, #bad P_1/f, #bad P_st (non-finite or negative)
+//            #bad S, #bad P_1/f, #bad P_st (non-finite or negative),
+//            #values that break the evenness of the real columns
 template <class T>
 __global__ __launch_bounds__(256) void stats_spectra_kernel(const T* __restrict__ sk,
                                                             const T* __restrict__ poof,
@@ -124,7 +125,7 @@ __global__ __launch_bounds__(256) void stats_spectra_kernel(const T* __restrict_
   __shared__ double sh[16];
   const int nh = nx / 2 + 1;
   const int64_t n = (int64_t)ny * nh;
-  double ms = INFINITY, mo = INFINITY, mf = INFINITY, bs = 0, bo = 0, bp = 0;
+  double ms = INFINITY, mo = INFINITY, mf = INFINITY, bs = 0, bo = 0, bp = 0, asym = 0;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
        i += (int64_t)gridDim.x * blockDim.x) {
     const int ky = (int)(i / nh), kx = (int)(i - (int64_t)ky * nh);
@@ -144,6 +145,14 @@ __global__ __launch_bounds__(256) void stats_spectra_kernel(const T* __restrict_
       f += (double)nx * p;
     }
     mf = fmin(mf, f);
+    // spectra of a real field are even in k: on the real columns k_x = 0 and
+    // nx/2 the value at -k_y must equal the one at k_y (and P_st is even)
+    if ((kx == 0 || kx == nx / 2) && ky > 0 && ky < ny / 2) {
+      const int64_t im = (int64_t)(ny - ky) * nh + kx;
+      if (!(sk[im] == sk[i])) asym += 1;
+      if (poof && !(poof[im] == poof[i])) asym += 1;
+      if (pst && kx == 0 && !(pst[ny - ky] == pst[ky])) asym += 1;
+    }
   }
   ms = block_reduce<RED_MIN>(ms, sh);
   mo = block_reduce<RED_MIN>(mo, sh);
@@ -151,9 +160,10 @@ __global__ __launch_bounds__(256) void stats_spectra_kernel(const T* __restrict_
   bs = block_reduce<RED_SUM>(bs, sh);
   bo = block_reduce<RED_SUM>(bo, sh);
   bp = block_reduce<RED_SUM>(bp, sh);
+  asym = block_reduce<RED_SUM>(asym, sh);
   if (threadIdx.x == 0) {
     double* o = part + 8 * blockIdx.x;
-    o[0] = ms; o[1] = mo; o[2] = mf; o[3] = bs; o[4] = bo; o[5] = bp; o[6] = 0; o[7] = 0;
+    o[0] = ms; o[1] = mo; o[2] = mf; o[3] = bs; o[4] = bo; o[5] = bp; o[6] = asym; o[7] = 0;
   }
 }
 
@@ -643,35 +653,63 @@ __global__ __launch_bounds__(TC * (NY / col_elems<T, NY>()), (min_waves<T, NY>()
     k.fk = a.fk;
     k.store_first = store_first;
     const cx<T> z = {(T)0, (T)0};
-    // the k_x = nx/2 half of the packed column (its own state)
-    if (packed) {
-      for (int q = 0; q < E; ++q) {
-        const int ky = t + NT * q;
-        const size_t idx = (size_t)kxn * NY + ky;
-        const int li = LM::at(ky);
-        cnl[li] = chain_mode<T, FK>(a, k, kxn, ky, idx, cnl[li], a.sc[idx],
-                             needNb ? a.nbA[idx] : (T)0, needP ? a.pst[ky] : (T)0,
-                             hasA ? ((cx<T>*)a.tA)[idx] : z, hasB ? ((cx<T>*)a.dA)[idx] : z,
-                             hasB ? ((cx<T>*)a.tB)[idx] : z);
+    if (!packed) {
+      // this column, in batches of loads
+#pragma unroll
+      for (int h = 0; h < E; h += HB) {
+        load_half(h);
+#pragma unroll
+        for (int q = 0; q < HB; ++q) {
+          const int ky = t + NT * (h + q);
+          const size_t idx = (size_t)kxc * NY + ky;
+          reg[h + q] = chain_mode<T, FK>(a, k, kxc, ky, idx, reg[h + q], sv[q], nv[q], pv[q],
+                                         ta[q], da[q], tb[q]);
+        }
       }
     }
-    // this column, in batches of loads
+    if (g == 0) {
+      // the packed column: the real-valued columns k_x = 0 (C0, in registers)
+      // and k_x = nx/2 (CN, in this column's LDS slots) are Hermitian in k_y,
+      // so the chain runs on k_y <= NY/2 only -- as many modes per thread as
+      // any other column, so this block is no straggler -- and the rest
+      // follows by conjugation.  The stored fields of k_y > NY/2 in these two
+      // columns are not updated (readers take the mirrored mode).
+      constexpr int EH = E / 2;  // registers q < EH hold k_y < NY/2
+      if (packed) {
 #pragma unroll
-    for (int h = 0; h < E; h += HB) {
-      load_half(h);
-#pragma unroll
-      for (int q = 0; q < HB; ++q) {
-        const int ky = t + NT * (h + q);
-        const size_t idx = (size_t)kxc * NY + ky;
-        reg[h + q] = chain_mode<T, FK>(a, k, kxc, ky, idx, reg[h + q], sv[q], nv[q], pv[q],
-                                       ta[q], da[q], tb[q]);
+        for (int q = 0; q <= EH; ++q) {
+          if (q == EH && t != 0) break;  // k_y = NY/2 on thread 0 only
+          const int ky = t + NT * q;
+          const int li = LM::at(ky);
+          const T ps = needP ? a.pst[ky] : (T)0;
+          const size_t i0 = (size_t)ky, iN = (size_t)kxn * NY + ky;
+          reg[q] = chain_mode<T, FK>(a, k, 0, ky, i0, reg[q], a.sc[i0],
+                                     needNb ? a.nbA[i0] : (T)0, ps,
+                                     hasA ? ((cx<T>*)a.tA)[i0] : z, hasB ? ((cx<T>*)a.dA)[i0] : z,
+                                     hasB ? ((cx<T>*)a.tB)[i0] : z);
+          cnl[li] = chain_mode<T, FK>(a, k, kxn, ky, iN, cnl[li], a.sc[iN],
+                                      needNb ? a.nbA[iN] : (T)0, ps,
+                                      hasA ? ((cx<T>*)a.tA)[iN] : z, hasB ? ((cx<T>*)a.dA)[iN] : z,
+                                      hasB ? ((cx<T>*)a.tB)[iN] : z);
+          // C0 of k_y in (0, NY/2) waits in the unused CN slot of NY - k_y
+          if (q < EH && ky > 0) cnl[LM::at(NY - ky)] = reg[q];
+        }
       }
-    }
-    if (packed) {
+      __syncthreads();
+      if (packed) {
 #pragma unroll
-      for (int q = 0; q < E; ++q) {
-        const cx<T> cv = cnl[LM::at(t + NT * q)];
-        reg[q] = cx<T>{reg[q].re - cv.im, reg[q].im + cv.re};
+        for (int q = 0; q < E; ++q) {
+          const int ky = t + NT * q;
+          cx<T> c0, cn;
+          if (ky <= NY / 2) {
+            c0 = reg[q];
+            cn = cnl[LM::at(ky)];
+          } else {
+            c0 = cconj(cnl[LM::at(ky)]);
+            cn = cconj(cnl[LM::at(NY - ky)]);
+          }
+          reg[q] = cx<T>{c0.re - cn.im, c0.im + cn.re};
+        }
       }
     }
   }
@@ -766,9 +804,13 @@ __global__ __launch_bounds__(kTCM * (NY / mon_elems<NY>())) void mon_col_kernel(
 #pragma unroll
   for (int q = 0; q < E; ++q) {
     const int ky = t + NT * q;
-    const size_t idx = (size_t)kx * NY + ky;
+    // the sweep keeps the real columns k_x = 0 and nx/2 for k_y <= NY/2 only:
+    // the other half is the conjugate of the mirrored mode
+    const bool mir = (kx == 0 || kx == m.nx / 2) && ky > NY / 2;
+    const size_t idx = (size_t)kx * NY + (mir ? NY - ky : ky);
     if (valid) {
-      const cx<T> v = tf[idx];
+      cx<T> v = tf[idx];
+      if (mir) v.im = -v.im;
       const double inv = 1.0 / ((double)m.sc[idx] + Tf);
       const cx<double> x = {(double)v.re * inv, (double)v.im * inv};
       const double f = (mode == MON_OUTPUT) ? (m.out_chain ? (double)m.sc[idx] : (double)m.sig[idx])

@@ -402,6 +402,7 @@ wf_status map_setup(Ctx* c, const wf_inputs* in, const wf_schedule* s, const voi
   if (r.pix[0] < 1) return WF_EINVAL;                             // no observed pixel
   if (r.pix[4] > 0) return WF_ENONFINITE;                         // NaN/Inf on observed pixels
   if (r.spec[3] > 0 || r.spec[4] > 0 || r.spec[5] > 0) return WF_EINVAL;  // bad spectra
+  if (r.spec[6] > 0) return WF_EINVAL;  // not even in k_y on the real columns
   if (r.pix[5] > 0) return WF_ENOTPD;                             // N_pix <= 0 observed
   wf_status ps = plan_chain(c, s, has_oof, has_st, r.pix, r.spec, &r.ch);
   if (ps != WF_OK) return ps;

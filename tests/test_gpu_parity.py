@@ -265,6 +265,25 @@ def test_error_codes(gpu_lib):
     q.s_k = q.s_k.copy()
     q.s_k[1, 1] = -1.0
     _expect(gpu_lib, "EINVAL", q)
+    # spectra of real fields are even in k: k_y and -k_y of the real columns
+    # k_x = 0 and nx/2 must agree, and the stripe spectrum must be even
+    q = synth.make_problem(64, 64, 1)
+    q.s_k = q.s_k.copy()
+    q.s_k[3, 0] *= 1.5
+    _expect(gpu_lib, "EINVAL", q)
+    q = synth.make_problem(64, 64, 1)
+    q.p_oof = q.p_oof.copy()
+    q.p_oof[61, 32] *= 1.5
+    _expect(gpu_lib, "EINVAL", q)
+    q = synth.make_problem(64, 64, 1)
+    q.p_stripe = q.p_stripe.copy()
+    q.p_stripe[5] *= 2.0
+    _expect(gpu_lib, "EINVAL", q)
+    q = synth.make_problem(64, 64, 1)
+    q.s_k = q.s_k.copy()
+    q.s_k[3, 1] *= 1.5  # k_x = 1 is complex: no constraint
+    s_ok, _, _, res = _run_both(gpu_lib, q, "f32", [10.0, 3.0, 1.0, 1.0], monitor_every=2)
+    assert _rel(s_ok, res.s) < TOL["f32"]
     ctx = gpu_lib.Context(64, 64, "f32")
     with pytest.raises(gpu_lib.WFError):
         ctx.solve(*_tensors(p, "f32"), schedule=gpu_lib.Schedule(max_sweeps=0))
