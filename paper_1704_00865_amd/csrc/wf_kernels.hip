@@ -168,20 +168,22 @@ __global__ __launch_bounds__(256) void stats_spectra_kernel(const T* __restrict_
 }
 
 // reduce per-block statistics in a fixed order; ops[j] says how column j
-// combines (sum / min / max)
-__global__ __launch_bounds__(64) void stats_finalize_kernel(const double* __restrict__ part, int nblk,
-                                                            int4 ops_lo, int4 ops_hi,
-                                                            double* __restrict__ out) {
-  const int j = threadIdx.x;
-  if (j >= 8) return;
+// combines (sum / min / max).  Wave j reduces column j: lane l takes blocks
+// l, l + 64, ..., then the lanes combine in a fixed butterfly.
+__global__ __launch_bounds__(512) void stats_finalize_kernel(const double* __restrict__ part, int nblk,
+                                                             int4 ops_lo, int4 ops_hi,
+                                                             double* __restrict__ out) {
+  const int j = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int ops[8] = {ops_lo.x, ops_lo.y, ops_lo.z, ops_lo.w, ops_hi.x, ops_hi.y, ops_hi.z, ops_hi.w};
   const int op = ops[j];
-  double r = part[j];
-  for (int b = 1; b < nblk; ++b) {
-    const double v = part[8 * b + j];
-    r = op == RED_SUM ? r + v : (op == RED_MIN ? fmin(r, v) : fmax(r, v));
-  }
-  out[j] = r;
+  auto comb = [op](double a, double b) {
+    return op == RED_SUM ? a + b : (op == RED_MIN ? fmin(a, b) : fmax(a, b));
+  };
+  double r = op == RED_SUM ? 0.0 : (op == RED_MIN ? INFINITY : -INFINITY);
+  for (int b = lane; b < nblk; b += 64) r = comb(r, part[8 * b + j]);
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) r = comb(r, __shfl_xor(r, off, 64));
+  if (lane == 0) out[j] = r;
 }
 
 // ---------------------------------------------------------------------------
@@ -787,10 +789,12 @@ __global__ __launch_bounds__(kTCM * (NY / mon_elems<NY>())) void mon_col_kernel(
   const MonArgs<T>& m = argv[blockIdx.y];
   constexpr int E = mon_elems<NY>();
   constexpr int NT = NY / E;
-  using LM = ldsmap<double, NY, E>;  // exchange-buffer index map
+  using LM = ldsmap<T, NY, E>;  // exchange-buffer index map
   constexpr int YS = LM::size;
   constexpr int TRTC = kTRM * kTCM;
-  __shared__ cx<double> lds[kTCM * YS];
+  __shared__ __align__(16) cx<T> lds[kTCM * YS];
+  constexpr bool LTW = lds_twiddles<T, NY>();
+  __shared__ cx<T> twl[LTW ? NY : 1];
   // residual: lambda of the chunk's last sweep; output: of the last sweep run
   double lamv = m.sch->lam_last;
   if (mode == MON_RESIDUAL && !monitor_active(m.sch, &lamv, m.lam)) return;
@@ -800,7 +804,12 @@ __global__ __launch_bounds__(kTCM * (NY / mon_elems<NY>())) void mon_col_kernel(
   const bool valid = kx < m.nx / 2 + 1;
   const double Tf = lamv * m.tau_first;
   const cx<T>* tf = (const cx<T>*)m.tfirst;
-  cx<double> rx[E], ry[E];
+  const cx<T>* twg = (const cx<T>*)m.twy;
+  if constexpr (LTW) stage_twiddles<T, NY, E>(twl, twg, tid, blockDim.x);
+  const cx<T>* tw = LTW ? (const cx<T>*)twl : twg;
+  // x = t / (S_c + lambda tau) and the Fourier-diagonal products are formed
+  // in float64 and rounded once to the transform precision
+  cx<T> rx[E], ry[E];
 #pragma unroll
   for (int q = 0; q < E; ++q) {
     const int ky = t + NT * q;
@@ -812,21 +821,22 @@ __global__ __launch_bounds__(kTCM * (NY / mon_elems<NY>())) void mon_col_kernel(
       cx<T> v = tf[idx];
       if (mir) v.im = -v.im;
       const double inv = 1.0 / ((double)m.sc[idx] + Tf);
-      const cx<double> x = {(double)v.re * inv, (double)v.im * inv};
+      const double xr = (double)v.re * inv, xi = (double)v.im * inv;
       const double f = (mode == MON_OUTPUT) ? (m.out_chain ? (double)m.sc[idx] : (double)m.sig[idx])
                                             : (double)m.sy[idx];
-      rx[q] = x;
-      ry[q] = cx<double>{x.re * f, x.im * f};
+      rx[q] = cx<T>{(T)xr, (T)xi};
+      ry[q] = cx<T>{(T)(xr * f), (T)(xi * f)};
     } else {
-      rx[q] = cx<double>{0.0, 0.0};
-      ry[q] = cx<double>{0.0, 0.0};
+      rx[q] = cx<T>{(T)0, (T)0};
+      ry[q] = cx<T>{(T)0, (T)0};
     }
   }
+  if constexpr (LTW) __syncthreads();
 #pragma unroll
   for (int field = 0; field < 2; ++field) {
-    cx<double>* reg = field == 0 ? rx : ry;
-    cx<double>* dst = field == 0 ? m.Mx : m.My;
-    fft<double, NY, true, E>(reg, lds + c * YS, t, m.twy);
+    cx<T>* reg = field == 0 ? rx : ry;
+    cx<T>* dst = (cx<T>*)(field == 0 ? m.Mx : m.My);
+    fft<T, NY, true, E, LTW>(reg, lds + c * YS, t, tw);
 #pragma unroll
     for (int q = 0; q < E; ++q) lds[c * YS + LM::at(t + NT * q)] = reg[q];
     __syncthreads();
@@ -848,19 +858,25 @@ __global__ __launch_bounds__(kTRM * (NX / mon_elems<NX>())) void mon_row_kernel(
   constexpr int KPm = KP<NX, kTCM>::value;
   constexpr int BANDm = kTRM * KPm;
   // the two bands are staged row-major, X rows then Y rows, with a row stride
-  // of 8 mod 16 values (rows 32 banks apart): reading a row's consecutive k_x
-  // and writing a tile's rows are then free of bank conflicts
+  // of 8 mod 16 values (rows 32 banks apart for 16-byte values, 16 for 8-byte
+  // ones): reading a row's consecutive k_x and writing a tile's rows are then
+  // free of bank conflicts
   constexpr int RSm = KPm + ((8 - KPm % 16) + 16) % 16;
-  using LM = ldsmap<double, NX, E>;  // exchange-buffer index map
+  using LM = ldsmap<T, NX, E>;  // exchange-buffer index map
   constexpr int XS = LM::size;
   constexpr int LDSN = (2 * kTRM * RSm > kTRM * XS) ? 2 * kTRM * RSm : kTRM * XS;
-  __shared__ cx<double> lds[LDSN];
+  __shared__ __align__(16) cx<T> lds[LDSN];
+  constexpr bool LTW = lds_twiddles<T, NX>();
+  __shared__ cx<T> twl[LTW ? NX : 1];
   __shared__ double sh[32];
   double lamv = 0.0;
   if (mode == MON_RESIDUAL && !monitor_active(m.sch, &lamv, m.lam)) return;
   const int tid = threadIdx.x, band = blockIdx.x;
-  const cx<double>* gx = m.Mx + (size_t)band * BANDm;
-  const cx<double>* gy = m.My + (size_t)band * BANDm;
+  const cx<T>* gx = (const cx<T>*)m.Mx + (size_t)band * BANDm;
+  const cx<T>* gy = (const cx<T>*)m.My + (size_t)band * BANDm;
+  const cx<T>* twg = (const cx<T>*)m.twx;
+  if constexpr (LTW) stage_twiddles<T, NX, E>(twl, twg, tid, blockDim.x);
+  const cx<T>* tw = LTW ? (const cx<T>*)twl : twg;
   for (int e = tid; e < BANDm; e += blockDim.x) {
     // tile order [kx / kTCM][row][kx % kTCM]
     const int g = e / (kTRM * kTCM), w = e - g * (kTRM * kTCM);
@@ -870,32 +886,32 @@ __global__ __launch_bounds__(kTRM * (NX / mon_elems<NX>())) void mon_row_kernel(
   }
   __syncthreads();
   const int r = tid / NT, t = tid - r * NT;
-  cx<double> reg[E];
+  cx<T> reg[E];
 #pragma unroll
   for (int q = 0; q < E; ++q) {
     const int k = t + NT * q;
     const bool hi = k > NX / 2;
     const int kx = hi ? NX - k : k;
     const int li = r * RSm + kx;
-    cx<double> X = lds[li], Y = lds[kTRM * RSm + li];
+    cx<T> X = lds[li], Y = lds[kTRM * RSm + li];
     if (kx == 0 || kx == NX / 2) {
-      X.im = 0.0;
-      Y.im = 0.0;
+      X.im = (T)0;
+      Y.im = (T)0;
     }
     if (hi) {
       X.im = -X.im;
       Y.im = -Y.im;
     }
-    reg[q] = cx<double>{X.re - Y.im, X.im + Y.re};
+    reg[q] = cx<T>{X.re - Y.im, X.im + Y.re};
   }
   __syncthreads();
-  fft<double, NX, true, E>(reg, lds + r * XS, t, m.twx);
+  fft<T, NX, true, E, LTW>(reg, lds + r * XS, t, tw);
   const int y = band * kTRM + r;
   double a_dd = 0.0, a_mx = 0.0;
 #pragma unroll
   for (int q = 0; q < E; ++q) {
     const size_t i = (size_t)y * NX + t + NT * q;
-    const double xv = reg[q].re * m.scale, yv = reg[q].im * m.scale;
+    const double xv = (double)reg[q].re * m.scale, yv = (double)reg[q].im * m.scale;
     if (mode == MON_OUTPUT) {
       s_out[i] = (T)yv;
     } else if (m.nbar2[i] >= (T)0) {

@@ -95,10 +95,10 @@ struct MonArgs {
   const T* d;           // [ny][nx]
   const T* npix;        // [ny][nx] caller's white variance
   const T* nbar2;       // [ny][nx] sign marks the mask
-  cx<double>* Mx;       // monitor transit, tiled [y/kTRM][kx/kTCM][kTRM][kTCM]
-  cx<double>* My;
-  const cx<double>* twx;  // float64 twiddles
-  const cx<double>* twy;
+  void* Mx;             // cx<T> monitor transit, tiled [y/kTRM][kx/kTCM][kTRM][kTCM]
+  void* My;
+  const void* twx;      // cx<T> twiddle tables (natural order)
+  const void* twy;
   const DevSched* sch;
   const double* lam;
   double* part;         // per-block (sum dd^2, sum masked x^2)

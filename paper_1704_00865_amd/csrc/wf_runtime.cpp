@@ -46,10 +46,8 @@ struct Ctx {
   void* nbar2 = nullptr;
   void* twx = nullptr;
   void* twy = nullptr;
-  cx<double>* twx_d = nullptr;
-  cx<double>* twy_d = nullptr;
-  cx<double>* Mx = nullptr;
-  cx<double>* My = nullptr;
+  void* Mx = nullptr;  // monitor transit, context precision
+  void* My = nullptr;
   double* part = nullptr;
   double* stats = nullptr;
   DevSched* sch = nullptr;
@@ -108,7 +106,7 @@ void make_table(std::vector<T>& out, int n) {
 
 void free_ctx(Ctx* c) {
   void* bufs[] = {c->B, c->tA, c->dA, c->tB, c->sc, c->nbA, c->sy, c->sig, c->nbar2, c->twx, c->twy,
-                  c->twx_d, c->twy_d, c->Mx, c->My, c->part, c->stats, c->sch, c->lam, c->trace,
+                  c->Mx, c->My, c->part, c->stats, c->sch, c->lam, c->trace,
                   c->alpha_sk, c->d_args, c->d_margs, c->d_ctrl};
   for (void* p : bufs)
     if (p) (void)hipFree(p);
@@ -162,10 +160,8 @@ wf_status create(const wf_shape* sh, Ctx** out) {
   A(c->nbar2, ny * nx * esz);
   A(c->twx, nx * 2 * esz);
   A(c->twy, ny * 2 * esz);
-  A(c->twx_d, nx * sizeof(cx<double>));
-  A(c->twy_d, ny * sizeof(cx<double>));
-  A(c->Mx, ny * c->kpm * sizeof(cx<double>));
-  A(c->My, ny * c->kpm * sizeof(cx<double>));
+  A(c->Mx, ny * c->kpm * 2 * esz);
+  A(c->My, ny * c->kpm * 2 * esz);
   const size_t npart = std::max<size_t>(2 * ny / kTRM, 16 * kStatBlocks);
   A(c->part, npart * sizeof(double));
   A(c->stats, 16 * sizeof(double));
@@ -186,19 +182,17 @@ wf_status create(const wf_shape* sh, Ctx** out) {
     return from_hip(e);
   }
   // twiddle tables, computed in double and rounded once
-  std::vector<double> tdx, tdy;
-  make_table(tdx, c->nx);
-  make_table(tdy, c->ny);
-  e = hipMemcpy(c->twx_d, tdx.data(), tdx.size() * 8, hipMemcpyHostToDevice);
-  if (e == hipSuccess) e = hipMemcpy(c->twy_d, tdy.data(), tdy.size() * 8, hipMemcpyHostToDevice);
   if (c->prec == WF_F64) {
-    if (e == hipSuccess) e = hipMemcpy(c->twx, tdx.data(), tdx.size() * 8, hipMemcpyHostToDevice);
+    std::vector<double> tdx, tdy;
+    make_table(tdx, c->nx);
+    make_table(tdy, c->ny);
+    e = hipMemcpy(c->twx, tdx.data(), tdx.size() * 8, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(c->twy, tdy.data(), tdy.size() * 8, hipMemcpyHostToDevice);
   } else {
     std::vector<float> fx, fy;
     make_table(fx, c->nx);
     make_table(fy, c->ny);
-    if (e == hipSuccess) e = hipMemcpy(c->twx, fx.data(), fx.size() * 4, hipMemcpyHostToDevice);
+    e = hipMemcpy(c->twx, fx.data(), fx.size() * 4, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(c->twy, fy.data(), fy.size() * 4, hipMemcpyHostToDevice);
   }
   if (e != hipSuccess) {
@@ -324,8 +318,8 @@ MonArgs<T> mon_args(Ctx* c, const wf_inputs* in, const Chain& ch) {
   m.nbar2 = (const T*)c->nbar2;
   m.Mx = c->Mx;
   m.My = c->My;
-  m.twx = c->twx_d;
-  m.twy = c->twy_d;
+  m.twx = c->twx;
+  m.twy = c->twy;
   m.sch = c->sch;
   m.lam = c->lam;
   m.part = c->part;
@@ -384,19 +378,32 @@ struct ShapeClass {
   int tile = kTileDefault;
 };
 
+// Validation statistics of one map's inputs, copied to the context's pinned
+// slot (stream-ordered; the caller waits).
+template <class T>
+hipError_t enqueue_stats(Ctx* c, const wf_inputs* in, hipStream_t st) {
+  hipError_t e = launch_stats<T>((const T*)in->d, (const T*)in->n_pix, in->mask, (const T*)in->s_k,
+                                 (const T*)in->p_oof, (const T*)in->p_stripe, c->ny, c->nx,
+                                 c->part, kStatBlocks, c->stats, c->stats + 8, st);
+  if (e != hipSuccess) return e;
+  return hipMemcpyAsync(c->h_stats, c->stats, 16 * sizeof(double), hipMemcpyDeviceToHost, st);
+}
+
 // Validation, tau_i, coefficients, schedule and zero/warm start of one map.
-// dsched: where this map's device schedule lives.
+// dsched: where this map's device schedule lives.  stats_ready: the map's
+// statistics are already in c->h_stats (a batch enqueues every map's
+// statistics and waits once).
 template <class T>
 wf_status map_setup(Ctx* c, const wf_inputs* in, const wf_schedule* s, const void* s_init,
-                    void* s_out, DevSched* dsched, MapRun<T>& r, hipStream_t st) {
+                    void* s_out, DevSched* dsched, MapRun<T>& r, hipStream_t st,
+                    bool stats_ready = false) {
   r.c = c;
   r.in = in;
   const bool has_oof = in->p_oof != nullptr, has_st = in->p_stripe != nullptr;
-  WF_TRY(launch_stats<T>((const T*)in->d, (const T*)in->n_pix, in->mask, (const T*)in->s_k,
-                         (const T*)in->p_oof, (const T*)in->p_stripe, c->ny, c->nx, c->part,
-                         kStatBlocks, c->stats, c->stats + 8, st));
-  WF_TRY(hipMemcpyAsync(c->h_stats, c->stats, 16 * sizeof(double), hipMemcpyDeviceToHost, st));
-  WF_TRY(hipStreamSynchronize(st));
+  if (!stats_ready) {
+    WF_TRY(enqueue_stats<T>(c, in, st));
+    WF_TRY(hipStreamSynchronize(st));
+  }
   std::memcpy(r.pix, c->h_stats, sizeof(r.pix));
   std::memcpy(r.spec, c->h_stats + 8, sizeof(r.spec));
   if (r.pix[0] < 1) return WF_EINVAL;                             // no observed pixel
@@ -669,9 +676,11 @@ wf_status solve_batch_t(Ctx** ctxs, int n, const wf_inputs* ins, const wf_schedu
   BT(hipMalloc((void**)&dmargs, (size_t)n * sizeof(MonArgs<T>)));
   BT(hipMalloc((void**)&dctrl, (size_t)n * sizeof(CtrlArgs)));
   BT(hipHostMalloc((void**)&hring, (size_t)kRing * n * sizeof(DevSched), hipHostMallocDefault));
+  for (int i = 0; i < n; ++i) BT(enqueue_stats<T>(ctxs[i], &ins[i], user_st));
+  BT(hipStreamSynchronize(user_st));
   for (int i = 0; i < n; ++i) {
     wf_status ms = map_setup<T>(ctxs[i], &ins[i], s, s_init ? s_init[i] : nullptr, s_out[i],
-                                dsch + i, runs[i], user_st);
+                                dsch + i, runs[i], user_st, true);
     if (ms != WF_OK) {
       (void)hipStreamSynchronize(user_st);
       cleanup();
