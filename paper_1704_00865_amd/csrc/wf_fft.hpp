@@ -24,6 +24,32 @@ struct cx {
   T re, im;
 };
 
+// Buffers reached through pointers stored in argument blocks in device memory
+// are generic to the compiler, which then emits flat loads and stores: their
+// completion is counted with the LDS operations, so every wait for an LDS
+// exchange also waits for outstanding memory traffic.  Kernels address such
+// buffers through global-memory pointers (gmem) instead.
+#define WF_GLOBAL __attribute__((address_space(1)))
+template <class T>
+__device__ __forceinline__ WF_GLOBAL T* gmem(T* p) {
+  return (WF_GLOBAL T*)p;
+}
+// complex loads and stores through either kind of pointer (a class object in
+// global memory is copied field by field)
+template <class T>
+__device__ __forceinline__ cx<T> ldc(const cx<T>* p) {
+  return *p;
+}
+template <class T>
+__device__ __forceinline__ cx<T> ldc(const WF_GLOBAL cx<T>* p) {
+  return cx<T>{p->re, p->im};
+}
+template <class T>
+__device__ __forceinline__ void stc(WF_GLOBAL cx<T>* p, cx<T> v) {
+  p->re = v.re;
+  p->im = v.im;
+}
+
 template <class T>
 __device__ __forceinline__ cx<T> operator+(cx<T> a, cx<T> b) { return {a.re + b.re, a.im + b.im}; }
 template <class T>
@@ -220,9 +246,8 @@ struct twp_offsets {
 
 // Fill the pass-major table twp (LDS, twp_offsets::size entries) from the
 // natural table tw; threads tid of nthr share the work.
-template <class T, int N, int E>
-__device__ __forceinline__ void stage_twiddles(cx<T>* twp, const cx<T>* __restrict__ tw, int tid,
-                                               int nthr) {
+template <class T, int N, int E, class TW>
+__device__ __forceinline__ void stage_twiddles(cx<T>* twp, TW tw, int tid, int nthr) {
   using PL = plan_for<N, E>;
   using O = twp_offsets<N, E>;
   for (int e = tid; e < O::size; e += nthr) {
@@ -237,16 +262,16 @@ __device__ __forceinline__ void stage_twiddles(cx<T>* twp, const cx<T>* __restri
       const int o = e - O::o4, m = 1 + o / O::p3, k = o - (m - 1) * O::p3;
       j = m * k * (N / (O::p3 * PL::r3));
     }
-    twp[e] = tw[j];
+    twp[e] = ldc(tw + j);
   }
 }
 
 // One Stockham pass.  reg: the thread's E values; lds: this transform's
 // padded exchange buffer; tw: the natural twiddle table (OFF < 0) or the
 // pass-major one, whose entries for this pass start at OFF.
-template <class T, int N, int R, int P, bool INV, bool LAST, int E = elems<N>::value, int OFF = -1>
-__device__ __forceinline__ void stockham_pass(cx<T>* reg, cx<T>* lds, int t,
-                                              const cx<T>* __restrict__ tw) {
+template <class T, int N, int R, int P, bool INV, bool LAST, int E = elems<N>::value, int OFF = -1,
+          class TW = const cx<T>*>
+__device__ __forceinline__ void stockham_pass(cx<T>* reg, cx<T>* lds, int t, TW tw) {
   constexpr int NT = N / E;
   constexpr int NB = E / R;
   using LM = ldsmap<T, N, E>;
@@ -262,7 +287,7 @@ __device__ __forceinline__ void stockham_pass(cx<T>* reg, cx<T>* lds, int t,
       constexpr int STEP = N / (P * R);
 #pragma unroll
       for (int m = 1; m < R; ++m) {
-        cx<T> w = OFF >= 0 ? tw[OFF + (m - 1) * P + k] : tw[m * k * STEP];
+        cx<T> w = ldc(OFF >= 0 ? tw + (OFF + (m - 1) * P + k) : tw + m * k * STEP);
         if (INV) w.im = -w.im;
         u[m] = cmul(u[m], w);
       }
@@ -289,25 +314,26 @@ __device__ __forceinline__ void stockham_pass(cx<T>* reg, cx<T>* lds, int t,
 // (it contains barriers); lds must hold ldsmap<T, N, E>::size elements per
 // transform and must not be in use by the caller.  tw is the natural
 // twiddle table, or the pass-major one of plan_for<N, E> when TWP.
-template <class T, int N, bool INV, int E = elems<N>::value, bool TWP = false>
-__device__ __forceinline__ void fft(cx<T>* reg, cx<T>* lds, int t, const cx<T>* __restrict__ tw) {
+template <class T, int N, bool INV, int E = elems<N>::value, bool TWP = false,
+          class TW = const cx<T>*>
+__device__ __forceinline__ void fft(cx<T>* reg, cx<T>* lds, int t, TW tw) {
   using PL = plan_for<N, E>;
   using O = twp_offsets<N, E>;
   constexpr int R0 = PL::r0, R1 = PL::r1, R2 = PL::r2, R3 = PL::r3;
   static_assert(R0 * R1 * R2 * R3 == N, "radix plan must multiply to N");
   constexpr int F2 = TWP ? O::o2 : -1, F3 = TWP ? O::o3 : -1, F4 = TWP ? O::o4 : -1;
   if constexpr (R2 == 1) {
-    stockham_pass<T, N, R0, 1, INV, false, E>(reg, lds, t, tw);
-    stockham_pass<T, N, R1, R0, INV, true, E, F2>(reg, lds, t, tw);
+    stockham_pass<T, N, R0, 1, INV, false, E, -1, TW>(reg, lds, t, tw);
+    stockham_pass<T, N, R1, R0, INV, true, E, F2, TW>(reg, lds, t, tw);
   } else if constexpr (R3 == 1) {
-    stockham_pass<T, N, R0, 1, INV, false, E>(reg, lds, t, tw);
-    stockham_pass<T, N, R1, R0, INV, false, E, F2>(reg, lds, t, tw);
-    stockham_pass<T, N, R2, R0 * R1, INV, true, E, F3>(reg, lds, t, tw);
+    stockham_pass<T, N, R0, 1, INV, false, E, -1, TW>(reg, lds, t, tw);
+    stockham_pass<T, N, R1, R0, INV, false, E, F2, TW>(reg, lds, t, tw);
+    stockham_pass<T, N, R2, R0 * R1, INV, true, E, F3, TW>(reg, lds, t, tw);
   } else {
-    stockham_pass<T, N, R0, 1, INV, false, E>(reg, lds, t, tw);
-    stockham_pass<T, N, R1, R0, INV, false, E, F2>(reg, lds, t, tw);
-    stockham_pass<T, N, R2, R0 * R1, INV, false, E, F3>(reg, lds, t, tw);
-    stockham_pass<T, N, R3, R0 * R1 * R2, INV, true, E, F4>(reg, lds, t, tw);
+    stockham_pass<T, N, R0, 1, INV, false, E, -1, TW>(reg, lds, t, tw);
+    stockham_pass<T, N, R1, R0, INV, false, E, F2, TW>(reg, lds, t, tw);
+    stockham_pass<T, N, R2, R0 * R1, INV, false, E, F3, TW>(reg, lds, t, tw);
+    stockham_pass<T, N, R3, R0 * R1 * R2, INV, true, E, F4, TW>(reg, lds, t, tw);
   }
 }
 

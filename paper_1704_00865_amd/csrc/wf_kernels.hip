@@ -262,6 +262,15 @@ template <class T>
 __device__ __forceinline__ void copy16(cx<T>* dst, const cx<T>* src) {
   *reinterpret_cast<uint4*>(dst) = *reinterpret_cast<const uint4*>(src);
 }
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+template <class T>
+__device__ __forceinline__ void copy16(cx<T>* dst, const WF_GLOBAL cx<T>* src) {
+  *reinterpret_cast<u32x4*>(dst) = *reinterpret_cast<const WF_GLOBAL u32x4*>(src);
+}
+template <class T>
+__device__ __forceinline__ void copy16(WF_GLOBAL cx<T>* dst, const cx<T>* src) {
+  *reinterpret_cast<WF_GLOBAL u32x4*>(dst) = *reinterpret_cast<const u32x4*>(src);
+}
 
 // ---------------------------------------------------------------------------
 // row kernel: inverse row FFT -> white-level update -> forward row FFT
@@ -330,25 +339,24 @@ __global__ __launch_bounds__((RW / 2) * (NX / row_elems<T, NX>()), (min_waves<T,
 
   T lt = (T)0;  // lambda * tau of the white level
   if constexpr (MODE == ROW_SWEEP) {
-    const DevSched* s = a.sch;
+    const WF_GLOBAL DevSched* s = gmem(a.sch);
     if (s->done) return;
     const int kk = s->base + k_local;
     if (kk >= s->max_sweeps) return;
-    lt = (T)(a.lam[kk] * a.tauW);
+    lt = (T)(gmem(a.lam)[kk] * a.tauW);
   }
   const int tid = threadIdx.x;
   const int blk = xcd_remap(blockIdx.x, gridDim.x, min(TR / RW, lines_share<T>(RW * TC)));
   const int y0 = blk * RW;
   const int r0 = y0 % TR;
-  cx<T>* gband = (cx<T>*)a.B + (size_t)(y0 / TR) * (TR * KPC) + r0 * TC;
-  const cx<T>* twg = (const cx<T>*)a.twx;
+  WF_GLOBAL cx<T>* gband = gmem((cx<T>*)a.B) + (size_t)(y0 / TR) * (TR * KPC) + r0 * TC;
+  const WF_GLOBAL cx<T>* twg = gmem((const cx<T>*)a.twx);
   const int p = tid / NT, t = tid - p * NT;
   const int ya = y0 + 2 * p;
   cx<T> reg[E];
   if constexpr (LTW) {
     stage_twiddles<T, NX, E>(twl, twg, tid, blockDim.x);
   }
-  const cx<T>* tw = LTW ? (const cx<T>*)twl : twg;
 
   if constexpr (MODE == ROW_SWEEP || MODE == ROW_C2R) {
     for (int e = tid * EPC; e < SUB; e += blockDim.x * EPC) {
@@ -381,7 +389,8 @@ __global__ __launch_bounds__((RW / 2) * (NX / row_elems<T, NX>()), (min_waves<T,
       reg[q] = cx<T>{A.re - Bv.im, A.im + Bv.re};
     }
     __syncthreads();
-    fft<T, NX, true, E, LTW>(reg, lds + p * XS, t, tw);
+    if constexpr (LTW) fft<T, NX, true, E, true>(reg, lds + p * XS, t, (const cx<T>*)twl);
+    else fft<T, NX, true, E, false>(reg, lds + p * XS, t, twg);
     const T sc = (T)a.scale;
     if constexpr (MODE == ROW_C2R) {
 #pragma unroll
@@ -395,16 +404,18 @@ __global__ __launch_bounds__((RW / 2) * (NX / row_elems<T, NX>()), (min_waves<T,
       // white-level update, data and coefficients loaded in batches of 8
       // (float32) or 4 (float64) values, to stay within the register budget
       constexpr int QB = sizeof(T) == 8 ? 4 : 8;
+      const WF_GLOBAL T* gd = gmem(a.d);
+      const WF_GLOBAL T* gn2 = gmem(a.nbar2);
 #pragma unroll
       for (int h = 0; h < E; h += QB) {
         T dv0[QB], dv1[QB], nb0[QB], nb1[QB];
 #pragma unroll
         for (int q = 0; q < QB; ++q) {
           const size_t i0 = (size_t)ya * NX + t + NT * (h + q);
-          dv0[q] = a.d[i0];
-          dv1[q] = a.d[i0 + NX];
-          nb0[q] = a.nbar2[i0];
-          nb1[q] = a.nbar2[i0 + NX];
+          dv0[q] = gd[i0];
+          dv1[q] = gd[i0 + NX];
+          nb0[q] = gn2[i0];
+          nb1[q] = gn2[i0 + NX];
         }
 #pragma unroll
         for (int q = 0; q < QB; ++q) {
@@ -422,7 +433,8 @@ __global__ __launch_bounds__((RW / 2) * (NX / row_elems<T, NX>()), (min_waves<T,
     }
     if constexpr (LTW) __syncthreads();
   }
-  fft<T, NX, false, E, LTW>(reg, lds + p * XS, t, tw);
+  if constexpr (LTW) fft<T, NX, false, E, true>(reg, lds + p * XS, t, (const cx<T>*)twl);
+  else fft<T, NX, false, E, false>(reg, lds + p * XS, t, twg);
 #pragma unroll
   for (int q = 0; q < E; ++q) lds[p * XS + LM::at(t + NT * q)] = reg[q];
   __syncthreads();
@@ -469,12 +481,12 @@ struct ChainCoef {
 // One mode: t_2 (white messenger, Fourier) in, field for the white level out.
 // Reads and writes the stored Fourier-side fields of this mode.
 template <class T, int FK>
-__device__ __forceinline__ cx<T> chain_mode(const SweepArgs<T>& a, const ChainCoef<T>& k, int kx,
+__device__ __forceinline__ cx<T> chain_mode(WF_GLOBAL cx<T>* tA, WF_GLOBAL cx<T>* dA,
+                                            WF_GLOBAL cx<T>* tB, const ChainCoef<T>& k, int kx,
                                             int ky, size_t idx, cx<T> t2, T s, T nbA, T pst,
                                             cx<T> tAo, cx<T> dAo, cx<T> tBo) {
-  cx<T>* tA = (cx<T>*)a.tA;
   if constexpr (FK == FK_NONE) {
-    if (k.store_first) tA[idx] = t2;
+    if (k.store_first) stc(tA + idx, t2);
     return cscale(t2, s / (s + k.TW));
   } else if constexpr (FK == FK_ARRAY_STRIPE) {
     const T nbB = (kx == 0 ? k.nxr * pst : (T)0) + k.cB;
@@ -483,9 +495,9 @@ __device__ __forceinline__ cx<T> chain_mode(const SweepArgs<T>& a, const ChainCo
     const cx<T> dAn = wavg(nbA, tBn, k.TB, tAo, (T)1 / (nbA + k.TB));
     const cx<T> so = cscale(tAo, s / (s + k.SA));
     const cx<T> tAn = wavg(k.TA, dAn, nbA, so, (T)1 / (nbA + k.TA));
-    ((cx<T>*)a.tB)[idx] = tBn;
-    ((cx<T>*)a.dA)[idx] = dAn;
-    tA[idx] = tAn;
+    stc(tB + idx, tBn);
+    stc(dA + idx, dAn);
+    stc(tA + idx, tAn);
     return dBn;
   } else {
     // one Fourier level: an array level or the stripe level
@@ -495,7 +507,7 @@ __device__ __forceinline__ cx<T> chain_mode(const SweepArgs<T>& a, const ChainCo
     const cx<T> dAn = wavg(nb, t2, k.TW, tAo, (T)1 / (nb + k.TW));
     const cx<T> so = cscale(tAo, s / (s + k.SA));
     const cx<T> tAn = wavg(k.TA, dAn, nb, so, (T)1 / (nb + k.TA));
-    tA[idx] = tAn;
+    stc(tA + idx, tAn);
     return dAn;
   }
 }
@@ -520,13 +532,14 @@ __global__ __launch_bounds__(TC * (NY / col_elems<T, NY>()), (min_waves<T, NY>()
   double lam = 0.0, lamp = 0.0;
   bool store_first = false;
   if constexpr (MODE == COL_SWEEP) {
-    const DevSched* s = a.sch;
+    const WF_GLOBAL DevSched* s = gmem(a.sch);
     if (s->done) return;
     const int base = s->base;
     const int kk = base + k_local;
     if (kk >= s->max_sweeps) return;
-    lam = a.lam[kk];
-    lamp = a.lam[kk > 0 ? kk - 1 : 0];
+    const WF_GLOBAL double* glam = gmem(a.lam);
+    lam = glam[kk];
+    lamp = glam[kk > 0 ? kk - 1 : 0];
     const int klast = min(base + s->K, s->max_sweeps) - 1;
     store_first = (kk == klast);
   }
@@ -538,13 +551,19 @@ __global__ __launch_bounds__(TC * (NY / col_elems<T, NY>()), (min_waves<T, NY>()
   const bool packed = (kxc == 0);
   const int nh = a.nx / 2 + 1;
   const int kxn = a.nx / 2;
-  cx<T>* gB = (cx<T>*)a.B;
-  const cx<T>* twg = (const cx<T>*)a.twy;
+  WF_GLOBAL cx<T>* gB = gmem((cx<T>*)a.B);
+  const WF_GLOBAL cx<T>* twg = gmem((const cx<T>*)a.twy);
+  // per-mode coefficients and stored fields
+  const WF_GLOBAL T* gsc = gmem(a.sc);
+  const WF_GLOBAL T* gnb = gmem(a.nbA);
+  const WF_GLOBAL T* gps = gmem(a.pst);
+  WF_GLOBAL cx<T>* gtA = gmem((cx<T>*)a.tA);
+  WF_GLOBAL cx<T>* gdA = gmem((cx<T>*)a.dA);
+  WF_GLOBAL cx<T>* gtB = gmem((cx<T>*)a.tB);
   cx<T> reg[E];
   if constexpr (LTW) {
     stage_twiddles<T, NY, E>(twl, twg, tid, blockDim.x);
   }
-  const cx<T>* tw = LTW ? (const cx<T>*)twl : twg;
 
   // per-mode state and coefficients of this column, loaded in batches of 8
   // modes, or 4 where the registers are scarce (float64, 24 values per
@@ -562,12 +581,12 @@ __global__ __launch_bounds__(TC * (NY / col_elems<T, NY>()), (min_waves<T, NY>()
     for (int q = 0; q < HB; ++q) {
       const int ky = t + NT * (h + q);
       const size_t idx = (size_t)kxc * NY + ky;
-      sv[q] = a.sc[idx];
-      nv[q] = needNb ? a.nbA[idx] : (T)0;
-      pv[q] = needP ? a.pst[ky] : (T)0;
-      ta[q] = hasA ? ((const cx<T>*)a.tA)[idx] : z0;
-      da[q] = hasB ? ((const cx<T>*)a.dA)[idx] : z0;
-      tb[q] = hasB ? ((const cx<T>*)a.tB)[idx] : z0;
+      sv[q] = gsc[idx];
+      nv[q] = needNb ? gnb[idx] : (T)0;
+      pv[q] = needP ? gps[ky] : (T)0;
+      ta[q] = hasA ? ldc(gtA + idx) : z0;
+      da[q] = hasB ? ldc(gdA + idx) : z0;
+      tb[q] = hasB ? ldc(gtB + idx) : z0;
     }
   };
 
@@ -614,7 +633,8 @@ __global__ __launch_bounds__(TC * (NY / col_elems<T, NY>()), (min_waves<T, NY>()
 #pragma unroll
     for (int q = 0; q < E; ++q) reg[q] = lds[c * YS + LM::at(t + NT * q)];
     __syncthreads();
-    fft<T, NY, false, E, LTW>(reg, lds + c * YS, t, tw);
+    if constexpr (LTW) fft<T, NY, false, E, true>(reg, lds + c * YS, t, (const cx<T>*)twl);
+    else fft<T, NY, false, E, false>(reg, lds + c * YS, t, twg);
   }
 
   // packed column (block 0, column 0): split Z = C0 + i CN into the k_x = 0
@@ -676,8 +696,8 @@ __global__ __launch_bounds__(TC * (NY / col_elems<T, NY>()), (min_waves<T, NY>()
         for (int q = 0; q < HB; ++q) {
           const int ky = t + NT * (h + q);
           const size_t idx = (size_t)kxc * NY + ky;
-          reg[h + q] = chain_mode<T, FK>(a, k, kxc, ky, idx, reg[h + q], sv[q], nv[q], pv[q],
-                                         ta[q], da[q], tb[q]);
+          reg[h + q] = chain_mode<T, FK>(gtA, gdA, gtB, k, kxc, ky, idx, reg[h + q], sv[q], nv[q],
+                                         pv[q], ta[q], da[q], tb[q]);
         }
       }
     }
@@ -695,16 +715,14 @@ __global__ __launch_bounds__(TC * (NY / col_elems<T, NY>()), (min_waves<T, NY>()
           if (q == EH && t != 0) break;  // k_y = NY/2 on thread 0 only
           const int ky = t + NT * q;
           const int li = LM::at(ky);
-          const T ps = needP ? a.pst[ky] : (T)0;
+          const T ps = needP ? gps[ky] : (T)0;
           const size_t i0 = (size_t)ky, iN = (size_t)kxn * NY + ky;
-          reg[q] = chain_mode<T, FK>(a, k, 0, ky, i0, reg[q], a.sc[i0],
-                                     needNb ? a.nbA[i0] : (T)0, ps,
-                                     hasA ? ((cx<T>*)a.tA)[i0] : z, hasB ? ((cx<T>*)a.dA)[i0] : z,
-                                     hasB ? ((cx<T>*)a.tB)[i0] : z);
-          cnl[li] = chain_mode<T, FK>(a, k, kxn, ky, iN, cnl[li], a.sc[iN],
-                                      needNb ? a.nbA[iN] : (T)0, ps,
-                                      hasA ? ((cx<T>*)a.tA)[iN] : z, hasB ? ((cx<T>*)a.dA)[iN] : z,
-                                      hasB ? ((cx<T>*)a.tB)[iN] : z);
+          reg[q] = chain_mode<T, FK>(gtA, gdA, gtB, k, 0, ky, i0, reg[q], gsc[i0],
+                                     needNb ? gnb[i0] : (T)0, ps, hasA ? ldc(gtA + i0) : z,
+                                     hasB ? ldc(gdA + i0) : z, hasB ? ldc(gtB + i0) : z);
+          cnl[li] = chain_mode<T, FK>(gtA, gdA, gtB, k, kxn, ky, iN, cnl[li], gsc[iN],
+                                      needNb ? gnb[iN] : (T)0, ps, hasA ? ldc(gtA + iN) : z,
+                                      hasB ? ldc(gdA + iN) : z, hasB ? ldc(gtB + iN) : z);
           // C0 of k_y in (0, NY/2) waits in the unused CN slot of NY - k_y
           if (q < EH && ky > 0) cnl[LM::at(NY - ky)] = reg[q];
         }
@@ -733,9 +751,9 @@ __global__ __launch_bounds__(TC * (NY / col_elems<T, NY>()), (min_waves<T, NY>()
     // level is s_init too, except for a chain without Fourier level, where it
     // is the signal-end field S_c (S_c + lambda_0 tau)^-1 s_init (or s_init
     // itself when s_init is that field)
-    cx<T>* tA = (cx<T>*)a.tA;
-    cx<T>* dA = (cx<T>*)a.dA;
-    cx<T>* tB = (cx<T>*)a.tB;
+    WF_GLOBAL cx<T>* tA = gtA;
+    WF_GLOBAL cx<T>* dA = gdA;
+    WF_GLOBAL cx<T>* tB = gtB;
     const T TW0 = (T)(lam_init * a.tauW);
 #pragma unroll
     for (int q = 0; q < E; ++q) {
@@ -749,14 +767,14 @@ __global__ __launch_bounds__(TC * (NY / col_elems<T, NY>()), (min_waves<T, NY>()
         cx<T> v = h == 0 ? reg[q] : cnl[LM::at(ky)];
         if (a.fk == FK_NONE) {
           if (!a.warm_chain) {
-            const T s = a.sc[idx];
+            const T s = gsc[idx];
             v = cscale(v, s / (s + TW0));
           }
         } else {
-          tA[idx] = v;
+          stc(tA + idx, v);
           if (a.fk == FK_ARRAY_STRIPE) {
-            dA[idx] = v;
-            tB[idx] = v;
+            stc(dA + idx, v);
+            stc(tB + idx, v);
           }
         }
         out[h] = v;
@@ -767,7 +785,8 @@ __global__ __launch_bounds__(TC * (NY / col_elems<T, NY>()), (min_waves<T, NY>()
 
   // the inverse transform reuses column 0's LDS region
   __syncthreads();
-  fft<T, NY, true, E, LTW>(reg, lds + c * YS, t, tw);
+  if constexpr (LTW) fft<T, NY, true, E, true>(reg, lds + c * YS, t, (const cx<T>*)twl);
+  else fft<T, NY, true, E, false>(reg, lds + c * YS, t, twg);
 #pragma unroll
   for (int q = 0; q < E; ++q) lds[c * YS + LM::at(t + NT * q)] = reg[q];
   __syncthreads();
@@ -788,8 +807,8 @@ __global__ __launch_bounds__(TC * (NY / col_elems<T, NY>()), (min_waves<T, NY>()
 // ---------------------------------------------------------------------------
 
 
-__device__ __forceinline__ bool monitor_active(const DevSched* s, double* lam_last,
-                                               const double* lam) {
+__device__ __forceinline__ bool monitor_active(const WF_GLOBAL DevSched* s, double* lam_last,
+                                               const WF_GLOBAL double* lam) {
   if (s->done) return false;
   const int klast = min(s->base + s->K, s->max_sweeps) - 1;
   *lam_last = lam[klast];
@@ -808,17 +827,19 @@ __global__ __launch_bounds__(kTCM * (NY / mon_elems<NY>())) void mon_col_kernel(
   constexpr bool LTW = lds_twiddles<T, NY>();
   __shared__ cx<T> twl[LTW ? NY : 1];
   // residual: lambda of the chunk's last sweep; output: of the last sweep run
-  double lamv = m.sch->lam_last;
-  if (mode == MON_RESIDUAL && !monitor_active(m.sch, &lamv, m.lam)) return;
+  double lamv = gmem(m.sch)->lam_last;
+  if (mode == MON_RESIDUAL && !monitor_active(gmem(m.sch), &lamv, gmem(m.lam))) return;
   const int tid = threadIdx.x, g = blockIdx.x, G = m.kpm / kTCM;
   const int c = tid / NT, t = tid - c * NT;
   const int kx = g * kTCM + c;
   const bool valid = kx < m.nx / 2 + 1;
   const double Tf = lamv * m.tau_first;
-  const cx<T>* tf = (const cx<T>*)m.tfirst;
-  const cx<T>* twg = (const cx<T>*)m.twy;
+  const WF_GLOBAL cx<T>* tf = gmem((const cx<T>*)m.tfirst);
+  const WF_GLOBAL T* msc = gmem(m.sc);
+  const WF_GLOBAL T* msy = gmem(m.sy);
+  const WF_GLOBAL T* msig = gmem(m.sig);
+  const WF_GLOBAL cx<T>* twg = gmem((const cx<T>*)m.twy);
   if constexpr (LTW) stage_twiddles<T, NY, E>(twl, twg, tid, blockDim.x);
-  const cx<T>* tw = LTW ? (const cx<T>*)twl : twg;
   // x = t / (S_c + lambda tau) and the Fourier-diagonal products are formed
   // in float64 and rounded once to the transform precision
   cx<T> rx[E], ry[E];
@@ -830,12 +851,12 @@ __global__ __launch_bounds__(kTCM * (NY / mon_elems<NY>())) void mon_col_kernel(
     const bool mir = (kx == 0 || kx == m.nx / 2) && ky > NY / 2;
     const size_t idx = (size_t)kx * NY + (mir ? NY - ky : ky);
     if (valid) {
-      cx<T> v = tf[idx];
+      cx<T> v = ldc(tf + idx);
       if (mir) v.im = -v.im;
-      const double inv = 1.0 / ((double)m.sc[idx] + Tf);
+      const double inv = 1.0 / ((double)msc[idx] + Tf);
       const double xr = (double)v.re * inv, xi = (double)v.im * inv;
-      const double f = (mode == MON_OUTPUT) ? (m.out_chain ? (double)m.sc[idx] : (double)m.sig[idx])
-                                            : (double)m.sy[idx];
+      const double f = (mode == MON_OUTPUT) ? (m.out_chain ? (double)msc[idx] : (double)msig[idx])
+                                            : (double)msy[idx];
       rx[q] = cx<T>{(T)xr, (T)xi};
       ry[q] = cx<T>{(T)(xr * f), (T)(xi * f)};
     } else {
@@ -847,15 +868,16 @@ __global__ __launch_bounds__(kTCM * (NY / mon_elems<NY>())) void mon_col_kernel(
 #pragma unroll
   for (int field = 0; field < 2; ++field) {
     cx<T>* reg = field == 0 ? rx : ry;
-    cx<T>* dst = (cx<T>*)(field == 0 ? m.Mx : m.My);
-    fft<T, NY, true, E, LTW>(reg, lds + c * YS, t, tw);
+    WF_GLOBAL cx<T>* dst = gmem((cx<T>*)(field == 0 ? m.Mx : m.My));
+    if constexpr (LTW) fft<T, NY, true, E, true>(reg, lds + c * YS, t, (const cx<T>*)twl);
+    else fft<T, NY, true, E, false>(reg, lds + c * YS, t, twg);
 #pragma unroll
     for (int q = 0; q < E; ++q) lds[c * YS + LM::at(t + NT * q)] = reg[q];
     __syncthreads();
     for (int e = tid; e < kTCM * NY; e += blockDim.x) {
       const int yb = e / TRTC, w = e - yb * TRTC;
       const int r = w / kTCM, cc = w - r * kTCM;
-      dst[((size_t)yb * G + g) * TRTC + w] = lds[cc * YS + LM::at(yb * kTRM + r)];
+      stc(dst + ((size_t)yb * G + g) * TRTC + w, lds[cc * YS + LM::at(yb * kTRM + r)]);
     }
     __syncthreads();
   }
@@ -864,7 +886,7 @@ __global__ __launch_bounds__(kTCM * (NY / mon_elems<NY>())) void mon_col_kernel(
 template <class T, int NX>
 __global__ __launch_bounds__(kTRM * (NX / mon_elems<NX>())) void mon_row_kernel(const MonArgs<T>* __restrict__ argv, int mode) {
   const MonArgs<T>& m = argv[blockIdx.y];
-  T* __restrict__ s_out = (T*)m.s_out;
+  WF_GLOBAL T* s_out = gmem((T*)m.s_out);
   constexpr int E = mon_elems<NX>();
   constexpr int NT = NX / E;
   constexpr int KPm = KP<NX, kTCM>::value;
@@ -882,19 +904,18 @@ __global__ __launch_bounds__(kTRM * (NX / mon_elems<NX>())) void mon_row_kernel(
   __shared__ cx<T> twl[LTW ? NX : 1];
   __shared__ double sh[32];
   double lamv = 0.0;
-  if (mode == MON_RESIDUAL && !monitor_active(m.sch, &lamv, m.lam)) return;
+  if (mode == MON_RESIDUAL && !monitor_active(gmem(m.sch), &lamv, gmem(m.lam))) return;
   const int tid = threadIdx.x, band = blockIdx.x;
-  const cx<T>* gx = (const cx<T>*)m.Mx + (size_t)band * BANDm;
-  const cx<T>* gy = (const cx<T>*)m.My + (size_t)band * BANDm;
-  const cx<T>* twg = (const cx<T>*)m.twx;
+  const WF_GLOBAL cx<T>* gx = gmem((const cx<T>*)m.Mx) + (size_t)band * BANDm;
+  const WF_GLOBAL cx<T>* gy = gmem((const cx<T>*)m.My) + (size_t)band * BANDm;
+  const WF_GLOBAL cx<T>* twg = gmem((const cx<T>*)m.twx);
   if constexpr (LTW) stage_twiddles<T, NX, E>(twl, twg, tid, blockDim.x);
-  const cx<T>* tw = LTW ? (const cx<T>*)twl : twg;
   for (int e = tid; e < BANDm; e += blockDim.x) {
     // tile order [kx / kTCM][row][kx % kTCM]
     const int g = e / (kTRM * kTCM), w = e - g * (kTRM * kTCM);
     const int rr = w / kTCM, kx = g * kTCM + (w - rr * kTCM);
-    lds[rr * RSm + kx] = gx[e];
-    lds[(kTRM + rr) * RSm + kx] = gy[e];
+    lds[rr * RSm + kx] = ldc(gx + e);
+    lds[(kTRM + rr) * RSm + kx] = ldc(gy + e);
   }
   __syncthreads();
   const int r = tid / NT, t = tid - r * NT;
@@ -917,7 +938,11 @@ __global__ __launch_bounds__(kTRM * (NX / mon_elems<NX>())) void mon_row_kernel(
     reg[q] = cx<T>{X.re - Y.im, X.im + Y.re};
   }
   __syncthreads();
-  fft<T, NX, true, E, LTW>(reg, lds + r * XS, t, tw);
+  if constexpr (LTW) fft<T, NX, true, E, true>(reg, lds + r * XS, t, (const cx<T>*)twl);
+  else fft<T, NX, true, E, false>(reg, lds + r * XS, t, twg);
+  const WF_GLOBAL T* mn2 = gmem(m.nbar2);
+  const WF_GLOBAL T* mnp = gmem(m.npix);
+  const WF_GLOBAL T* md = gmem(m.d);
   const int y = band * kTRM + r;
   double a_dd = 0.0, a_mx = 0.0;
 #pragma unroll
@@ -926,8 +951,8 @@ __global__ __launch_bounds__(kTRM * (NX / mon_elems<NX>())) void mon_row_kernel(
     const double xv = (double)reg[q].re * m.scale, yv = (double)reg[q].im * m.scale;
     if (mode == MON_OUTPUT) {
       s_out[i] = (T)yv;
-    } else if (m.nbar2[i] >= (T)0) {
-      const double dd = yv + (double)m.npix[i] * xv - (double)m.d[i];
+    } else if (mn2[i] >= (T)0) {
+      const double dd = yv + (double)mnp[i] * xv - (double)md[i];
       a_dd += dd * dd;
     } else {
       a_mx += xv * xv;
@@ -937,8 +962,9 @@ __global__ __launch_bounds__(kTRM * (NX / mon_elems<NX>())) void mon_row_kernel(
   a_dd = block_reduce<RED_SUM>(a_dd, sh);
   a_mx = block_reduce<RED_SUM>(a_mx, sh);
   if (tid == 0) {
-    m.part[2 * band] = a_dd;
-    m.part[2 * band + 1] = a_mx;
+    WF_GLOBAL double* part = gmem(m.part);
+    part[2 * band] = a_dd;
+    part[2 * band + 1] = a_mx;
   }
 }
 
