@@ -225,6 +225,26 @@ def main():
     import paper_1704_00865_amd as wf
     import synth
 
+    warm_maps = None
+    if not a.skip_warm:
+        # drawn in forked workers before anything touches the GPU
+        n_w = a.warm_size
+        workers = min(16, os.cpu_count() or 1)
+        print(f"[bench] warm start: generating {a.warm_train}+{a.warm_test} maps of {n_w}^2 "
+              f"({workers} processes)", file=sys.stderr, flush=True)
+        tg = time.perf_counter()
+
+        def draw(seeds):
+            out = []
+            for c0 in range(0, len(seeds), 256):
+                out += synth.make_problems(n_w, n_w, seeds[c0:c0 + 256], workers=workers,
+                                           mask_frac=0.10)
+                print(f"[bench] warm start: {len(out)}/{len(seeds)} maps drawn "
+                      f"({time.perf_counter() - tg:.1f} s)", file=sys.stderr, flush=True)
+            return out
+        warm_maps = (draw(list(range(10000, 10000 + a.warm_train))),
+                     draw(list(range(20000, 20000 + a.warm_test))))
+
     wf.load()
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
@@ -380,10 +400,8 @@ def main():
     if not a.skip_warm:
         from paper_1704_00865_amd import warmstart
         n_w = a.warm_size
-        print(f"[bench] warm start: generating {a.warm_train}+{a.warm_test} maps of {n_w}^2",
-              file=sys.stderr, flush=True)
-        trp = [synth.make_problem(n_w, n_w, 10000 + i, mask_frac=0.10) for i in range(a.warm_train)]
-        tep = [synth.make_problem(n_w, n_w, 20000 + i, mask_frac=0.10) for i in range(a.warm_test)]
+        trp, tep = warm_maps
+        warm_maps = None
         warm = warmstart.experiment(trp, tep, epochs=a.warm_epochs, batch=16, lr=2e-3,
                                     log=lambda m: print(f"[bench] {m}", file=sys.stderr, flush=True))
         warm["recipe"] = (f"{n_w}^2 maps, three noise terms, 10% disc mask; train seeds "

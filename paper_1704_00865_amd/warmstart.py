@@ -61,7 +61,7 @@ def _inputs(problems, ms: MapSet, i: int):
                 p_stripe=t(p.p_stripe), mask=ms.mask[i])
 
 
-def solve_set(problems, ms: MapSet, schedule: Schedule, s_init=None, group: int = 64):
+def solve_set(problems, ms: MapSet, schedule: Schedule, s_init=None, group: int = 64, log=None):
     """Solve every map of the set with one schedule in batches of ``group``
     maps, from zero or from the warm starts s_init [n, h, w].  Each map
     stops on its own.  Returns (solutions [n, h, w], list of reports)."""
@@ -78,6 +78,8 @@ def solve_set(problems, ms: MapSet, schedule: Schedule, s_init=None, group: int 
                            schedule=schedule, outs=[out[i] for i in idx],
                            s_inits=None if s_init is None else [s_init[i] for i in idx])
         reps += r
+        if log and n > group:
+            log(f"solved {len(reps)}/{n} maps")
     for c in ctxs:
         c.close()
     return out, reps
@@ -170,7 +172,7 @@ def experiment(train_problems: Sequence, test_problems: Sequence, *, precision: 
     te = stack_problems(test_problems, precision)
     tsched = Schedule(lambda0=lam0, shrink=shrink, rtol=target_rtol, max_sweeps=max_sweeps,
                       monitor_every=16, chain="augmented", chain_field=True)
-    tr.s, rtr = solve_set(train_problems, tr, tsched)
+    tr.s, rtr = solve_set(train_problems, tr, tsched, log=log)
     torch.cuda.synchronize()
     t_gen = time.perf_counter() - t0
     if log:
@@ -186,7 +188,7 @@ def experiment(train_problems: Sequence, test_problems: Sequence, *, precision: 
     # reference solutions of the test maps and the predictions
     esched = Schedule(lambda0=lam0, shrink=shrink, rtol=eval_rtol, max_sweeps=max_sweeps,
                       monitor_every=16, chain="augmented", chain_field=True)
-    s_ref, rzero = solve_set(test_problems, te, esched)
+    s_ref, rzero = solve_set(test_problems, te, esched, log=log)
     pred = predict(net, te, max(batch, 8))
     err_pred = rel_error(pred, s_ref)
     err_zero = np.ones(te.n)
@@ -213,7 +215,7 @@ def experiment(train_problems: Sequence, test_problems: Sequence, *, precision: 
     for l0 in warm_lam0:
         sch = Schedule(lambda0=l0, shrink=shrink, rtol=eval_rtol, max_sweeps=max_sweeps,
                        monitor_every=16, chain="augmented", chain_field=True)
-        _, rw = solve_set(test_problems, te, sch, s_init=pred)
+        _, rw = solve_set(test_problems, te, sch, s_init=pred, log=log)
         res["warm"].append({"lambda0": l0,
                             "sweeps_mean": float(np.mean([r["sweeps"] for r in rw])),
                             "converged": int(sum(r["status"] == "OK" for r in rw))})
@@ -223,7 +225,7 @@ def experiment(train_problems: Sequence, test_problems: Sequence, *, precision: 
     # reference: the converged field itself as the start, at lambda = 1
     sch = Schedule(lambda0=1.0, shrink=shrink, rtol=eval_rtol, max_sweeps=max_sweeps,
                    monitor_every=16, chain="augmented", chain_field=True)
-    _, rx = solve_set(test_problems, te, sch, s_init=s_ref)
+    _, rx = solve_set(test_problems, te, sch, s_init=s_ref, log=log)
     res["exact_start"] = {"lambda0": 1.0, "sweeps_mean": float(np.mean([r["sweeps"] for r in rx]))}
     best = min(res["warm"], key=lambda r: (-r["converged"], r["sweeps_mean"]))
     res["best_warm_lambda0"] = best["lambda0"]

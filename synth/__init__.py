@@ -11,6 +11,7 @@ from .maps import (  # noqa: F401
     Problem,
     l_of_modes,
     make_problem,
+    make_problems,
     make_stationary_problem,
     named_config,
     pixel_size_rad,

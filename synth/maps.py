@@ -237,3 +237,27 @@ def uneven_batch(sizes=(256, 768, 1536), per_size: int = 16, base_seed: int = 40
             out.append(make_problem(n, n, seed, oof_level=lvl, white_sigma=lvl / 2.0))
             i += 1
     return out
+
+
+def _compact_problem(args):
+    ny, nx, seed, kw = args
+    p = make_problem(ny, nx, seed, **kw)
+    f32 = np.float32
+    return Problem(d=p.d.astype(f32), s_k=p.s_k.astype(f32), n_pix=p.n_pix.astype(f32),
+                   p_oof=None if p.p_oof is None else p.p_oof.astype(f32),
+                   p_stripe=None if p.p_stripe is None else p.p_stripe.astype(f32),
+                   mask=p.mask, s_true=None, meta=p.meta)
+
+
+def make_problems(ny: int, nx: int, seeds, *, workers: int = 1, **kw):
+    """make_problem for many seeds, in ``workers`` forked processes when
+    workers > 1 (call it before the process uses a GPU).  The arrays come back
+    as float32 (exact: every solver input is float32-representable) and
+    without the signal realisation, to keep large sets small."""
+    jobs = [(ny, nx, int(s), kw) for s in seeds]
+    if workers <= 1:
+        return [_compact_problem(j) for j in jobs]
+    import multiprocessing as mp
+    with mp.get_context("fork").Pool(workers) as pool:
+        return pool.map(_compact_problem, jobs, chunksize=max(1, len(jobs) // (4 * workers)))
+
