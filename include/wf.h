@@ -23,7 +23,8 @@
  *     the covariance of a real field does;
  *   - the stripe covariance is the variance of each unitary 1-D DFT mode of
  *     the row value f(y), [ny] in FFT order (stripe map n(x, y) = f(y));
- *   - sizes: nx, ny powers of two in [64, 4096] (FP64 path: up to 2048);
+ *   - sizes: nx, ny powers of two in [64, 4096] (FP64 path: up to 2048), or
+ *     384, 768, 1536 (a radix-3 pass); other sizes give WF_EUNSUPPORTED;
  *   - every pointer in wf_inputs, s_init and s_out is a DEVICE pointer owned
  *     by the caller; arrays are float (WF_F32) or double (WF_F64) as the
  *     context's precision says; the mask is uint8 (1 observed, 0 masked);
