@@ -246,9 +246,10 @@ __global__ __launch_bounds__(256) void prep_spectra_kernel(const T* __restrict__
 // map a block index to a work index so that the `per` work items whose data
 // share HBM lines run on the same XCD (blocks go round-robin to the 8 XCDs)
 __device__ __forceinline__ int xcd_remap(int b, int n, int per) {
-  if (per <= 1 || (n % (8 * per)) != 0) return b;
+  const int span = 8 * per;
+  if (per <= 1 || b >= (n / span) * span) return b;  // a remainder keeps its order
   const int x = b & 7, s = b >> 3;
-  return (s / per) * (8 * per) + x * per + (s % per);
+  return (s / per) * span + x * per + (s % per);
 }
 
 template <class T>
@@ -829,7 +830,9 @@ __global__ __launch_bounds__(kTCM * (NY / mon_elems<NY>())) void mon_col_kernel(
   // residual: lambda of the chunk's last sweep; output: of the last sweep run
   double lamv = gmem(m.sch)->lam_last;
   if (mode == MON_RESIDUAL && !monitor_active(gmem(m.sch), &lamv, gmem(m.lam))) return;
-  const int tid = threadIdx.x, g = blockIdx.x, G = m.kpm / kTCM;
+  const int tid = threadIdx.x, G = m.kpm / kTCM;
+  // the transit tiles of neighbouring blocks share HBM lines: keep them on one XCD
+  const int g = xcd_remap(blockIdx.x, G, lines_share<T>(TRTC));
   const int c = tid / NT, t = tid - c * NT;
   const int kx = g * kTCM + c;
   const bool valid = kx < m.nx / 2 + 1;
