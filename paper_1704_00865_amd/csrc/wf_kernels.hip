@@ -293,12 +293,13 @@ constexpr int row_elems() {
   return (sizeof(T) == 4 && (N == 1024 || N == 2048)) ? 8 : elems<N>::value;
 }
 
-// values per thread of the column kernel's transforms: the default (8 was
-// measured slower at 2048: 37.6 vs 36.5 us; this kernel's per-mode chain
-// keeps more state per value than the row kernel's)
+// values per thread of the column kernel's transforms: 8 for the float32
+// lengths 1024 and 2048, with four waves per SIMD and the per-mode state
+// loaded two modes at a time (every wave of a 2048^2 sweep is then resident
+// at once: 27.3 instead of 31.1 us per launch), else the default
 template <class T, int N>
 constexpr int col_elems() {
-  return elems<N>::value;
+  return (sizeof(T) == 4 && (N == 1024 || N == 2048)) ? 8 : elems<N>::value;
 }
 
 // values per thread of the float64 monitor's transforms: 8 at 1024-4096
@@ -314,6 +315,12 @@ constexpr int mon_elems() {
 template <class T, int N>
 constexpr int min_waves() {
   return (sizeof(T) == 8 && elems<N>::value == 24) ? 1 : 2;
+}
+// waves per SIMD the column kernel is built for: four with 8 values per
+// thread, else as above
+template <class T, int N>
+constexpr int col_min_waves() {
+  return col_elems<T, N>() == 8 ? 4 : min_waves<T, N>();
 }
 
 template <class T, int NX, int TR, int TC, int RW, int MODE>
@@ -517,7 +524,7 @@ template <class T>
 __device__ __forceinline__ cx<T> cconj(cx<T> v) { return cx<T>{v.re, -v.im}; }
 
 template <class T, int NY, int TR, int TC, int MODE, int FK>
-__global__ __launch_bounds__(TC * (NY / col_elems<T, NY>()), (min_waves<T, NY>())) void col_kernel(const SweepArgs<T>* __restrict__ argv, int k_local,
+__global__ __launch_bounds__(TC * (NY / col_elems<T, NY>()), (col_min_waves<T, NY>())) void col_kernel(const SweepArgs<T>* __restrict__ argv, int k_local,
     cx<T>* __restrict__ spec, double lam_init) {
   const SweepArgs<T>& a = argv[blockIdx.y];  // one map per grid row
   constexpr int E = col_elems<T, NY>();
@@ -568,8 +575,9 @@ __global__ __launch_bounds__(TC * (NY / col_elems<T, NY>()), (min_waves<T, NY>()
 
   // per-mode state and coefficients of this column, loaded in batches of 8
   // modes, or 4 where the registers are scarce (float64, 24 values per
-  // thread, or 4096 points; 8 spilled there)
-  constexpr int HB = (sizeof(T) == 8 || E == 24 || NY >= 4096) ? 4 : 8;
+  // thread, or 4096 points; 8 spilled there), or 2 with 8 values per thread
+  // (four waves per SIMD leave 128 registers)
+  constexpr int HB = E == 8 ? 2 : ((sizeof(T) == 8 || E == 24 || NY >= 4096) ? 4 : 8);
   constexpr bool hasA = FK != FK_NONE;
   constexpr bool hasB = FK == FK_ARRAY_STRIPE;
   constexpr bool needNb = FK == FK_ARRAY || FK == FK_ARRAY_STRIPE;
