@@ -18,12 +18,16 @@ extern const TileCfg kTiles[kNumTiles];
 // Every launch covers nmaps maps of one shape and chain kind: argv is a
 // DEVICE array of nmaps argument blocks (blockIdx.y selects one); a / m is a
 // host copy of one of them, for the sizes.
+// e0, e1 (optional, sweep modes): events the dispatch itself records at the
+// kernel's start and end.
 template <class T>
 hipError_t launch_row(int cfg, int mode, const SweepArgs<T>& a, const SweepArgs<T>* argv,
-                      int nmaps, int k_local, const T* xin, T* xout, hipStream_t st);
+                      int nmaps, int k_local, const T* xin, T* xout, hipStream_t st,
+                      hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
 template <class T>
 hipError_t launch_col(int cfg, int mode, const SweepArgs<T>& a, const SweepArgs<T>* argv,
-                      int nmaps, int k_local, void* spec, double lam_init, hipStream_t st);
+                      int nmaps, int k_local, void* spec, double lam_init, hipStream_t st,
+                      hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
 template <class T>
 hipError_t launch_mon_col(const MonArgs<T>& m, const MonArgs<T>* argv, int nmaps, int mode,
                           hipStream_t st);

@@ -485,8 +485,9 @@ wf_status map_setup(Ctx* c, const wf_inputs* in, const wf_schedule* s, const voi
 }
 
 // One chunk: K sweeps of every class, then the monitor of every class and
-// the controller of every map.  ev (optional): 5 timing events around the
-// first sweep's row and column launches of class 0 and around the monitor.
+// the controller of every map.  ev (optional): 6 timing events, recorded by
+// the first sweep's row and column launches of class 0 themselves (start,
+// end) and around the monitor.
 template <class T>
 wf_status enqueue_chunk(std::vector<ShapeClass<T>>& cls, const std::vector<MapRun<T>>& runs,
                         const CtrlArgs* ctrl_argv, int nmaps, int K, hipEvent_t* ev,
@@ -495,21 +496,21 @@ wf_status enqueue_chunk(std::vector<ShapeClass<T>>& cls, const std::vector<MapRu
     for (size_t i = 0; i < cls.size(); ++i) {
       const SweepArgs<T>& a0 = runs[cls[i].maps[0]].a;
       const int n = (int)cls[i].maps.size();
-      if (ev && k == 0 && i == 0) WF_TRY(hipEventRecord(ev[0], st));
-      WF_TRY(launch_row<T>(cls[i].tile, ROW_SWEEP, a0, cls[i].argv, n, k, nullptr, nullptr, st));
-      if (ev && k == 0 && i == 0) WF_TRY(hipEventRecord(ev[1], st));
-      WF_TRY(launch_col<T>(cls[i].tile, COL_SWEEP, a0, cls[i].argv, n, k, nullptr, 0.0, st));
-      if (ev && k == 0 && i == 0) WF_TRY(hipEventRecord(ev[2], st));
+      const bool timed = ev && k == 0 && i == 0;
+      WF_TRY(launch_row<T>(cls[i].tile, ROW_SWEEP, a0, cls[i].argv, n, k, nullptr, nullptr, st,
+                           timed ? ev[0] : nullptr, timed ? ev[1] : nullptr));
+      WF_TRY(launch_col<T>(cls[i].tile, COL_SWEEP, a0, cls[i].argv, n, k, nullptr, 0.0, st,
+                           timed ? ev[2] : nullptr, timed ? ev[3] : nullptr));
     }
   }
-  if (ev) WF_TRY(hipEventRecord(ev[3], st));
+  if (ev) WF_TRY(hipEventRecord(ev[4], st));
   for (auto& cl : cls) {
     const MonArgs<T>& m0 = runs[cl.maps[0]].m;
     WF_TRY(launch_mon_col<T>(m0, cl.margv, (int)cl.maps.size(), MON_RESIDUAL, st));
     WF_TRY(launch_mon_row<T>(m0, cl.margv, (int)cl.maps.size(), MON_RESIDUAL, st));
   }
   WF_TRY(launch_controller(ctrl_argv, nmaps, st));
-  if (ev) WF_TRY(hipEventRecord(ev[4], st));
+  if (ev) WF_TRY(hipEventRecord(ev[5], st));
   return WF_OK;
 }
 
@@ -575,10 +576,10 @@ wf_status solve_t(Ctx* c, const wf_inputs* in, const wf_schedule* s, const void*
       c->prof_ev.push_back(e);
     }
   }
-  const int prof_chunks = kProfSlots / 5;
+  const int prof_chunks = kProfSlots / 6;
   int launched = 0;
   for (int ci = 0; ci < r.n_chunks; ++ci) {
-    hipEvent_t* ev = (prof && ci < prof_chunks) ? &c->prof_ev[5 * ci] : nullptr;
+    hipEvent_t* ev = (prof && ci < prof_chunks) ? &c->prof_ev[6 * ci] : nullptr;
     wf_status es = enqueue_chunk<T>(cls, runs, (const CtrlArgs*)c->d_ctrl, 1, K, ev, st);
     if (es != WF_OK) return es;
     const int slot = ci % kRing;
@@ -609,11 +610,11 @@ wf_status solve_t(Ctx* c, const wf_inputs* in, const wf_schedule* s, const void*
       const int last_chunk = fin.sweeps_done > 0 ? (fin.sweeps_done - 1) / K : 0;
       const int nsamp = std::min(std::min(launched, prof_chunks), last_chunk + 1);
       for (int ci = 0; ci < nsamp; ++ci) {
-        hipEvent_t* ev = &c->prof_ev[5 * ci];
+        hipEvent_t* ev = &c->prof_ev[6 * ci];
         float t01 = 0, t12 = 0, t34 = 0;
         WF_TRY(hipEventElapsedTime(&t01, ev[0], ev[1]));
-        WF_TRY(hipEventElapsedTime(&t12, ev[1], ev[2]));
-        WF_TRY(hipEventElapsedTime(&t34, ev[3], ev[4]));
+        WF_TRY(hipEventElapsedTime(&t12, ev[2], ev[3]));
+        WF_TRY(hipEventElapsedTime(&t34, ev[4], ev[5]));
         rep->kernel_ms[0] += t01;
         rep->kernel_ms[1] += t12;
         rep->kernel_ms[2] += t34;
