@@ -103,6 +103,15 @@ def _args():
     return ap.parse_args()
 
 
+def cooling_lambdas(n_cool, n_total, lam0=1.0e4):
+    """The fixed cooling schedule the timed solves run (Section 2 cooling):
+    lambda_k = lam0^(1 - k/n_cool) for k < n_cool, then 1 up to n_total."""
+    lam = []
+    for k in range(n_total):
+        lam.append(lam0 ** (1.0 - k / n_cool) if k < n_cool else 1.0)
+    return lam
+
+
 def column_bytes(ny, nx, esz=4):
     """Algorithmic HBM bytes of one column-kernel launch (three-level chain):
     transit buffer read + write, t_1, d_0, t_0 read + write (complex), S and
@@ -118,7 +127,7 @@ def row_bytes(ny, nx, esz=4):
     return ny * nx * 2 * esz + ny * nh * 2 * 2 * esz
 
 
-def bench_batch(wf, oracle, synth, torch, dev, a):
+def bench_batch(wf, synth, torch, dev, a):
     """48 independent maps (16 each of 256^2, 768^2, 1536^2) in one batched
     solve: the same float32 three-level chain and 500-sweep cooling schedule
     as the single-map workload.  Compared with solving the same maps one
@@ -133,7 +142,7 @@ def bench_batch(wf, oracle, synth, torch, dev, a):
                 p_stripe=t(p.p_stripe)) for p in probs]
     ctxs = [wf.Context(p.d.shape[0], p.d.shape[1], "f32", device=dev) for p in probs]
     outs = [torch.empty(p.d.shape, dtype=torch.float32, device=dev) for p in probs]
-    lams = list(oracle.cooling_ramp(400, a.sweeps, 1.0e4))
+    lams = cooling_lambdas(400, a.sweeps, 1.0e4)
     sched = wf.Schedule(lambdas=lams, rtol=0.0, max_sweeps=a.sweeps,
                         monitor_every=a.monitor_every)
     wf.solve_batch(ctxs, pbs, schedule=sched, outs=outs)
@@ -221,7 +230,6 @@ def main():
         sys.exit(2)
     import torch
 
-    import oracle
     import paper_1704_00865_amd as wf
     import synth
 
@@ -258,8 +266,8 @@ def main():
             torch.tensor(p.mask, dtype=torch.uint8, device=dev))
     out = torch.empty((n, n), dtype=torch.float32, device=dev)
     ctx = wf.Context(n, n, "f32", device=dev)
-    lams = list(oracle.cooling_ramp(400, a.sweeps, 1.0e4)) if a.sweeps > 400 else \
-        list(oracle.cooling_ramp(a.sweeps * 4 // 5, a.sweeps, 1.0e4))
+    lams = cooling_lambdas(400, a.sweeps, 1.0e4) if a.sweeps > 400 else \
+        cooling_lambdas(a.sweeps * 4 // 5, a.sweeps, 1.0e4)
     sched = wf.Schedule(lambdas=lams, rtol=0.0, max_sweeps=a.sweeps,
                         monitor_every=a.monitor_every, chain=a.chain)
 
@@ -394,7 +402,7 @@ def main():
 
     batch = None
     if not a.skip_batch:
-        batch = bench_batch(wf, oracle, synth, torch, dev, a)
+        batch = bench_batch(wf, synth, torch, dev, a)
 
     warm = None
     if not a.skip_warm:
@@ -410,6 +418,9 @@ def main():
 
     cpu = None
     if not a.skip_cpu:
+        # the CPU baseline is the float64 oracle itself (test infrastructure,
+        # imported by this leg only)
+        import oracle
         cores = min(16, os.cpu_count() or 1)
         oracle.bases.set_workers(cores)
         st = oracle.setup(p, oracle.Settings(chain=a.chain))

@@ -19,11 +19,12 @@ Contents and what pins each part (tests marked ``not gpu``):
                 form; the one-step EW limit (Section 3.1); the joint objective
                 never increases under a single update; rho -> 0 iff the
                 chi^2 gradient vanishes; the profile identity min J = chi^2.
+                It also holds the two-level merged chain and the augmented-signal
+                chain (Appendix A shortcuts, ``Settings.chain``), pinned by
+                reaching the dense solution's fixed point.
 * ``direct``    the Wiener filter by its definition (dense Cholesky, closed
                 form), chi^2 and its gradient.  Pinned by exact small cases
                 (1-pixel algebra, white-noise-only Fourier closed form).
-* ``variants``  the two-level merged chain and the augmented-signal chain
-                (Appendix A shortcuts); pinned by sharing the fixed point.
 * ``warmnet``   the convolutional warm-start predictor (not from the paper:
                 the iteration may start anywhere, Section 2): circular 3x3
                 convolutions, pooling, upsampling, forward and reverse-mode
@@ -48,6 +49,7 @@ from .messenger import (  # noqa: F401
     init_state,
     inverse_noise_weight,
     joint_objective,
+    next_lambda,
     setup,
     solve,
     sweep,

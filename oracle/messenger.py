@@ -348,6 +348,24 @@ class AdaptiveSchedule:
         return float(self.lam0)
 
 
+def next_lambda(schedule: AdaptiveSchedule, lam: float, prev: Optional[tuple], k: int,
+                dd2: float) -> tuple:
+    """One decision of the Section 3.3 recipe at a residual check after sweep
+    k (0-based) with squared residual dd2 = Delta d^T Delta d.  ``prev`` is
+    (k, dd2) of the previous check, or None at the first one.
+
+    The paper waits until Delta d^T Delta d changes by less than 1e-2 per
+    iteration and then lowers lam to lam^0.7.  With checks every few sweeps
+    the per-iteration change is the change since the previous check divided
+    by the sweeps between them, relative to dd2.  lam^0.7 only approaches 1,
+    so lam is set to 1 once lam - 1 < snap.  Returns (new lam, new prev)."""
+    if prev is not None and abs(dd2 - prev[1]) < schedule.plateau * (k - prev[0]) * dd2:
+        lam = lam ** schedule.shrink
+        if lam - 1.0 < schedule.snap:
+            lam = 1.0
+    return lam, (k, dd2)
+
+
 def cooling_ramp(n_cool: int, n_total: int, lam0: float = 1.0e4) -> np.ndarray:
     """lam_k = lam0^(1 - k/n_cool) for k < n_cool, then 1 up to n_total."""
     k = np.arange(n_total, dtype=np.float64)
@@ -402,12 +420,7 @@ def solve(problem, schedule, *, settings: Settings = Settings(),
                 res.converged = True
                 break
             if adaptive:
-                if prev is not None and abs(dg.dd2 - prev[1]) < \
-                        schedule.plateau * (k - 1 - prev[0]) * dg.dd2:
-                    lam = lam ** schedule.shrink
-                    if lam - 1.0 < schedule.snap:
-                        lam = 1.0
-                prev = (k - 1, dg.dd2)
+                lam, prev = next_lambda(schedule, lam, prev, k - 1, dg.dd2)
     res.s = final_chain_field(st, x, lam) if chain_field else final_signal(st, x, lam)
     res.sweeps = k
     res.state = x

@@ -559,3 +559,102 @@ def test_projected_dense_limit_matches_closed_form():
     c = direct.wiener_projected_dense(r)
     d = direct.wiener_dense(r)
     assert np.linalg.norm(c - d) / np.linalg.norm(d) < 1e-10
+
+
+# --------------------------------------------------------------------------
+# the adaptive cooling rule of Section 3.3, on hand-built residual sequences
+# --------------------------------------------------------------------------
+
+def _replay(sched, ks, dd2s, lam0):
+    """lambda in force after each residual check, by oracle.next_lambda."""
+    lam, prev, out = lam0, None, []
+    for k, v in zip(ks, dd2s):
+        lam, prev = oracle.next_lambda(sched, lam, prev, k, v)
+        out.append(lam)
+    return out
+
+
+def test_adaptive_rule_shrinks_exactly_on_a_one_percent_plateau():
+    """Section 3.3: lambda starts large; whenever Delta d^T Delta d changes by
+    less than 1e-2 per iteration, lambda is lowered to lambda^0.7.  Checks
+    after every sweep; the expected values are written out by hand."""
+    sched = oracle.AdaptiveSchedule(lam0=1e4, shrink=0.7, plateau=1e-2, snap=1e-3)
+    dd2 = [100.0, 90.0, 89.5, 89.0, 88.0, 101.0, 100.0]
+    got = _replay(sched, range(len(dd2)), dd2, 1e4)
+    l1 = 10.0 ** 2.8           # (1e4)^0.7
+    l2 = 10.0 ** (2.8 * 0.7)   # (1e4)^(0.7^2)
+    expect = [1e4,             # first check: nothing to compare with
+              1e4,             # 10 / 90 = 11 % per sweep
+              l1,              # 0.5 / 89.5 = 0.56 % per sweep: plateau
+              l2,              # 0.5 / 89 = 0.56 %: plateau again
+              l2,              # 1 / 88 = 1.14 %: still moving
+              l2,              # 13 / 101: moving
+              l2]              # 1 / 100 is exactly 1 %: not below it
+    np.testing.assert_allclose(got, expect, rtol=1e-14)
+
+
+def test_adaptive_rule_counts_sweeps_between_checks():
+    """With a check every 4 sweeps the change per iteration is the change
+    since the last check over 4: 3 in 4 sweeps at dd2 = 97 is 0.77 % per
+    sweep (plateau), 4 in 4 sweeps at 93 is 1.08 % (not)."""
+    sched = oracle.AdaptiveSchedule(lam0=1e4, shrink=0.7, plateau=1e-2, snap=1e-3)
+    got = _replay(sched, [3, 7, 11], [100.0, 97.0, 93.0], 1e4)
+    np.testing.assert_allclose(got, [1e4, 10.0 ** 2.8, 10.0 ** 2.8], rtol=1e-14)
+
+
+def test_adaptive_rule_snaps_to_one_and_needs_26_shrinks_from_1e4():
+    """lambda^0.7 only approaches 1; the reading here sets lambda = 1 once
+    lambda - 1 < 1e-3.  1.0015^0.7 = 1.00105 stays, its next power 1.00073
+    snaps.  From 1e4, 0.7^n ln(1e4) < ln(1 + 1e-3) first holds at n = 26."""
+    sched = oracle.AdaptiveSchedule(lam0=1.0015, shrink=0.7, plateau=1e-2, snap=1e-3)
+    got = _replay(sched, [0, 1, 2], [5.0, 5.0, 5.0], 1.0015)
+    assert got[0] == 1.0015
+    assert got[1] == pytest.approx(1.0015 ** 0.7, rel=1e-15) and got[1] - 1.0 > 1e-3
+    assert got[2] == 1.0
+    sched = oracle.AdaptiveSchedule(lam0=1e4)
+    lams = _replay(sched, range(40), [7.0] * 40, 1e4)
+    n_shrinks = sum(1 for a, b in zip([1e4] + lams, lams) if b < a)
+    assert n_shrinks == 26
+    assert lams[26] == 1.0 and lams[25] > 1.0
+    assert lams[-1] == 1.0
+
+
+def test_solve_follows_the_adaptive_rule():
+    """The lambdas an adaptive oracle solve ran match the rule replayed on
+    the residuals of its own trace (the wiring of solve)."""
+    p = _easy_three_term(mask=True)
+    sched = oracle.AdaptiveSchedule(lam0=1e3, plateau=5e-2)
+    K = 3
+    r = oracle.solve(p, sched, settings=oracle.Settings(chain="augmented"), max_sweeps=300,
+                     monitor_every=K)
+    ks = [t[0] for t in r.trace]
+    lam_after = _replay(sched, ks, [t[3] for t in r.trace], 1e3)
+    # lambda of the sweeps after each check is the rule's output there
+    for (k, lam_at, *_), nxt in zip(r.trace[1:], lam_after[:-1]):
+        assert lam_at == nxt
+    assert r.trace[0][1] == 1e3 and r.trace[-1][1] < 1e3
+
+
+# --------------------------------------------------------------------------
+# the start is not critical (Section 2): warm starts reach the same solution
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("chain,mask", [("three", False), ("augmented", True)])
+@pytest.mark.parametrize("start", ["truth", "constant"])
+def test_warm_start_converges_to_the_dense_solution(chain, mask, start):
+    """Section 2 states that the initial values do not matter for the
+    result.  From the true signal, and from a constant 50 uK field, the
+    iteration reaches the dense Cholesky Wiener solution."""
+    p = _easy_three_term(mask=mask)
+    sd = direct.wiener_dense(p)
+    s0 = p.s_true if start == "truth" else np.full(p.d.shape, 50.0)
+    r = oracle.solve(p, oracle.AdaptiveSchedule(lam0=1e3, plateau=1e-3),
+                     settings=oracle.Settings(chain=chain), s_init=s0, max_sweeps=40000,
+                     monitor_every=4, rtol=1e-12, full_residual=True)
+    assert r.converged
+    assert np.linalg.norm(r.s - sd) / np.linalg.norm(sd) < 1e-9
+    # the warm start did change the path: its first residual differs from
+    # the zero start's
+    z = oracle.solve(p, oracle.AdaptiveSchedule(lam0=1e3, plateau=1e-3),
+                     settings=oracle.Settings(chain=chain), max_sweeps=4, monitor_every=4)
+    assert r.trace[0][2] != z.trace[0][2]
