@@ -128,6 +128,14 @@ typedef struct {         /* HOST struct filled by wf_solve */
   double rho_mask;       /* nu |(1-m) S^-1 s| / |m d|, nu = max observed white variance */
   double dd2;            /* sum over observed pixels of (d_rec - d)^2                   */
   double d2;             /* sum over observed pixels of d^2                             */
+  double chi2_joint;     /* J_lambda: -2 log of the joint probability of the state      */
+                         /*   (eqn 2mess_prob): s^T S^-1 s plus, for every link of the  */
+                         /*   chain, difference^T C^-1 difference (C = T_i or Nbar_i),  */
+                         /*   at the last check's lambda, summed in float64; each sweep */
+                         /*   lowers it at fixed lambda (Appendix A), and at lambda = 1 */
+                         /*   its minimum over the messengers is chi^2(s) (Section 2).  */
+                         /*   Pixels with Nbar_white = 0 add nothing (t is d there)     */
+  double masked_x_norm;  /* |(1-m) S^-1 s|: zero at the Wiener solution                 */
   double tau[3];         /* messenger variances (1/f or merged, stripe, white); 0 absent*/
   double phi;            /* white floor moved to the stripe level                       */
   double kernel_ms[4];   /* profiling (wf_ctx_set_profiling): summed durations of the   */
@@ -148,8 +156,9 @@ void wf_schedule_default(wf_schedule* sch);
  * field starts at s_init; by Section 2 the start does not change the
  * solution), or NULL for the zero start of Section 2.  s_out: DEVICE
  * [ny*nx].  rep: HOST, may be
- * NULL.  trace: HOST [5 * ceil(max_sweeps / monitor_every)] rows of
- * (sweep index, lambda, rho, dd2, rho_mask), or NULL. */
+ * NULL.  trace: HOST [6 * ceil(max_sweeps / monitor_every)] rows of
+ * (sweep index, lambda, rho, dd2, rho_mask, chi2_joint), one per residual
+ * check, or NULL. */
 wf_status wf_solve(void* ctx, const wf_inputs* in, const wf_schedule* sch,
                    const void* s_init, void* s_out, wf_report* rep,
                    double* trace, hipStream_t stream);

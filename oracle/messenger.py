@@ -386,7 +386,8 @@ class Result:
 def solve(problem, schedule, *, settings: Settings = Settings(),
           s_init: Optional[np.ndarray] = None, max_sweeps: int = 1000,
           monitor_every: int = 1, rtol: float = 0.0,
-          full_residual: bool = False, chain_field: bool = False) -> Result:
+          full_residual: bool = False, chain_field: bool = False,
+          record_joint: bool = False) -> Result:
     """Iterate sweeps under a cooling schedule.
 
     Every ``monitor_every`` sweeps (and after the last sweep) the residual is
@@ -397,6 +398,8 @@ def solve(problem, schedule, *, settings: Settings = Settings(),
     the augmented chain, where u = s + N_F x).
     An adaptive schedule changes lam only at those points:
     if |dd2 - dd2_prev| < plateau * (sweeps since prev) * dd2, lam <- lam^shrink.
+    With ``record_joint`` each trace record also holds the joint objective
+    J_lam of the state (eqn 2mess_prob) as a sixth value.
     """
     st = setup(problem, settings)
     lam = schedule.first()
@@ -413,7 +416,10 @@ def solve(problem, schedule, *, settings: Settings = Settings(),
         k += 1
         if k % monitor_every == 0 or k == max_sweeps:
             dg = diagnostics(st, x, lam)
-            res.trace.append((k - 1, lam, dg.rho, dg.dd2, dg.rho_mask))
+            rec = (k - 1, lam, dg.rho, dg.dd2, dg.rho_mask)
+            if record_joint:
+                rec = rec + (joint_objective(st, x, lam),)
+            res.trace.append(rec)
             if not np.isfinite(dg.dd2):
                 break
             if lam == 1.0 and (dg.rho_full if full_residual else dg.rho) <= rtol:

@@ -28,6 +28,8 @@ _lib = None
 STATUS = {0: "OK", 1: "NOT_CONVERGED", -1: "EINVAL", -2: "ENOTPD", -3: "ENONFINITE",
           -4: "EDEVICE", -5: "ENOMEM", -6: "EUNSUPPORTED"}
 CHAINS = {"three": 0, "merged": 1, "augmented": 2}
+# columns of a trace row: sweep, lambda, rho, dd2, rho_mask, chi2_joint
+TRACE_COLS = 6
 
 
 class WFError(RuntimeError):
@@ -62,7 +64,8 @@ class _Report(ctypes.Structure):
                 ("n_records", ctypes.c_int32), ("n_levels", ctypes.c_int32),
                 ("lam", ctypes.c_double), ("rho", ctypes.c_double),
                 ("rho_mask", ctypes.c_double), ("dd2", ctypes.c_double),
-                ("d2", ctypes.c_double), ("tau", ctypes.c_double * 3),
+                ("d2", ctypes.c_double), ("chi2_joint", ctypes.c_double),
+                ("masked_x_norm", ctypes.c_double), ("tau", ctypes.c_double * 3),
                 ("phi", ctypes.c_double), ("kernel_ms", ctypes.c_double * 4),
                 ("kernel_launches", ctypes.c_int32 * 4)]
 
@@ -185,7 +188,8 @@ def _inputs(d, s_k, n_pix, p_oof, p_stripe, mask):
 def _report(rep) -> dict:
     return dict(status=STATUS[rep.status], sweeps=rep.sweeps, n_records=rep.n_records,
                 n_levels=rep.n_levels, lam=rep.lam, rho=rep.rho, rho_mask=rep.rho_mask,
-                dd2=rep.dd2, d2=rep.d2, tau=list(rep.tau), phi=rep.phi,
+                dd2=rep.dd2, d2=rep.d2, chi2_joint=rep.chi2_joint,
+                masked_x_norm=rep.masked_x_norm, tau=list(rep.tau), phi=rep.phi,
                 kernel_ms=list(rep.kernel_ms), kernel_launches=list(rep.kernel_launches))
 
 
@@ -304,7 +308,7 @@ class Context:
         import torch
         sch, keep = schedule._c()
         nrec = -(-schedule.max_sweeps // schedule.monitor_every)
-        trace = np.zeros((nrec, 5), dtype=np.float64)
+        trace = np.zeros((nrec, TRACE_COLS), dtype=np.float64)
         rep = _Report()
         with torch.cuda.device(self.device):
             st = fn(self._h, ctypes.byref(inp), ctypes.byref(sch),

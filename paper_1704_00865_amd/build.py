@@ -17,7 +17,12 @@ INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libwf.so")
 BUILD_DIR = os.path.join(PKG, "_build")
 
-SOURCES = ["wf_kernels.hip", "wf_runtime.cpp", "wf_nn.hip"]
+# (source, object, extra defines): the sweep kernels are compiled in two
+# parts, float32 and float64, in parallel
+SOURCES = [("wf_kernels.hip", "wf_kernels_f32.o", ("WF_PART=1",)),
+           ("wf_kernels.hip", "wf_kernels_f64.o", ("WF_PART=2",)),
+           ("wf_runtime.cpp", "wf_runtime.o", ()),
+           ("wf_nn.hip", "wf_nn.o", ())]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950",
@@ -37,7 +42,7 @@ def _hipcc() -> str:
     raise RuntimeError("hipcc not found")
 
 
-def build(verbose: bool = False, jobs: int = 2, defines=(), out: str = LIB,
+def build(verbose: bool = False, jobs: int = 4, defines=(), out: str = LIB,
           build_dir: str = BUILD_DIR) -> str:
     """Compile every source for gfx950 and link the shared library.  Always
     recompiles (objects go to a temporary folder that is removed after).
@@ -46,10 +51,10 @@ def build(verbose: bool = False, jobs: int = 2, defines=(), out: str = LIB,
     os.makedirs(build_dir, exist_ok=True)
     objs = []
     procs = []
-    for src in SOURCES:
-        obj = os.path.join(build_dir, os.path.splitext(src)[0] + ".o")
+    for src, oname, part in SOURCES:
+        obj = os.path.join(build_dir, oname)
         objs.append(obj)
-        cmd = [hipcc, "-x", "hip", *HIPCC_FLAGS, *[f"-D{d}" for d in defines],
+        cmd = [hipcc, "-x", "hip", *HIPCC_FLAGS, *[f"-D{d}" for d in (*part, *defines)],
                "-I", INCLUDE, "-I", CSRC, "-c",
                os.path.join(CSRC, src), "-o", obj]
         if verbose:

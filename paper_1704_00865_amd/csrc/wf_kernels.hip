@@ -23,17 +23,26 @@
 // messenger covariances are multiples of the identity, so the update
 // coefficients do not depend on that scale.
 //
-// The residual monitor runs in float64 from the stored state: x = S^-1 s =
-// t_A / (S_chain + T_A) and y = (S + N_Fourier) x go through float64 inverse
-// transforms, and Delta d = y + N_white x - d (Section 2) is summed over
-// observed pixels; x is summed over masked ones.  A one-block controller
-// then applies the cooling schedule on the device.
+// The residual monitor starts from the stored state: x = S^-1 s =
+// t_A / (S_chain + T_A) and y = (S + N_Fourier) x are formed per mode in
+// float64, rounded once to the path's precision and taken to pixel space by
+// inverse transforms of that precision; Delta d = y + N_white x - d
+// (Section 2) is then summed in float64 over observed pixels, and x^2 over
+// masked ones.  A one-block controller applies the cooling schedule on the
+// device.
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <stdint.h>
 
 #include "wf_fft.hpp"
 #include "wf_kernels.hpp"
+
+// The build compiles this file twice, with WF_PART = 1 (float32 kernels and
+// the precision-free ones) and WF_PART = 2 (float64 kernels), so that the two
+// halves compile in parallel; without a definition both are built.
+#ifndef WF_PART
+#define WF_PART 3
+#endif
 
 namespace wf {
 
@@ -47,6 +56,36 @@ __device__ __forceinline__ T white_update(T d, T nb, T d1, T lt) {
   // masked pixel (Nbar = inf, stored as a negative sentinel): t_2 = d_1
   if (nb < (T)0) return d1;
   return d1 + (lt / (nb + lt)) * (d - d1);
+}
+
+// The joint objective J_lambda (eqn 2mess_prob, the quadratic form that the
+// sweep minimises one field at a time) of the state after a sweep, summed in
+// float64 from the values the sweep computed:
+//   |t_0|^2 / (S_chain + T_0)           (the s terms, s = S_c (S_c + T_0)^-1 t_0)
+//   + sum over links of |difference|^2 / covariance,
+// the Fourier-diagonal links per mode in the column kernel, the white level's
+// link to the data per pixel in the row kernel.  A masked pixel (infinite
+// Nbar) adds nothing, nor does one with Nbar_2 = 0, whose exact update puts
+// t_2 on the data.
+template <class T>
+__device__ __forceinline__ double white_term(T d, T nb, T t2) {
+  if (!(nb > (T)0)) return 0.0;
+  const double r = (double)d - (double)t2;
+  return r * r / (double)nb;
+}
+
+// wave sum; lane 0 leaves it in sh[wave]
+__device__ __forceinline__ void wave_partial(double v, double* sh) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+}
+
+// the block's wave partials in a fixed order (after a barrier)
+__device__ __forceinline__ double sum_partials(const double* sh, int nthreads) {
+  double r = 0.0;
+  for (int w = 0; w < (nthreads + 63) >> 6; ++w) r += sh[w];
+  return r;
 }
 
 // ---------------------------------------------------------------------------
@@ -170,6 +209,7 @@ __global__ __launch_bounds__(256) void stats_spectra_kernel(const T* __restrict_
 // reduce per-block statistics in a fixed order; ops[j] says how column j
 // combines (sum / min / max).  Wave j reduces column j: lane l takes blocks
 // l, l + 64, ..., then the lanes combine in a fixed butterfly.
+#if WF_PART & 1
 __global__ __launch_bounds__(512) void stats_finalize_kernel(const double* __restrict__ part, int nblk,
                                                              int4 ops_lo, int4 ops_hi,
                                                              double* __restrict__ out) {
@@ -185,6 +225,11 @@ __global__ __launch_bounds__(512) void stats_finalize_kernel(const double* __res
   for (int off = 32; off > 0; off >>= 1) r = comb(r, __shfl_xor(r, off, 64));
   if (lane == 0) out[j] = r;
 }
+#else
+__global__ __launch_bounds__(512) void stats_finalize_kernel(const double* __restrict__ part, int nblk,
+                                                             int4 ops_lo, int4 ops_hi,
+                                                             double* __restrict__ out);
+#endif
 
 // ---------------------------------------------------------------------------
 // setup: per-pixel and per-mode coefficients
@@ -302,8 +347,9 @@ constexpr int col_elems() {
   return (sizeof(T) == 4 && (N == 1024 || N == 2048)) ? 8 : elems<N>::value;
 }
 
-// values per thread of the float64 monitor's transforms: 8 at 1024-4096
-// (measured 12% faster than 16 at 2048: 99 vs 113 us per check)
+// values per thread of the monitor's transforms (path precision): 8 at
+// 1024-4096 (measured 12% faster than 16 at 2048 when the monitor ran its
+// transforms in float64: 99 vs 113 us per check)
 template <int N>
 constexpr int mon_elems() {
   return (N == 1024 || N == 2048 || N == 4096) ? 8 : elems<N>::value;
@@ -345,14 +391,20 @@ __global__ __launch_bounds__((RW / 2) * (NX / row_elems<T, NX>()), (min_waves<T,
   constexpr bool LTW = lds_twiddles<T, NX>();
   __shared__ cx<T> twl[LTW ? NX : 1];
 
+  constexpr bool SW = MODE == ROW_SWEEP || MODE == ROW_SWEEP_J;
+  constexpr bool JV = MODE == ROW_SWEEP_J;
   T lt = (T)0;  // lambda * tau of the white level
-  if constexpr (MODE == ROW_SWEEP) {
+  bool jdo = false;  // this sweep closes its chunk: sum the pixel term of J
+  if constexpr (SW) {
     const WF_GLOBAL DevSched* s = gmem(a.sch);
     if (s->done) return;
     const int kk = s->base + k_local;
     if (kk >= s->max_sweeps) return;
     lt = (T)(gmem(a.lam)[kk] * a.tauW);
+    if constexpr (JV) jdo = kk == min(s->base + s->K, s->max_sweeps) - 1;
   }
+  __shared__ double jsh[JV ? 16 : 1];
+  double jacc = 0.0;
   const int tid = threadIdx.x;
   const int blk = xcd_remap(blockIdx.x, gridDim.x, min(TR / RW, lines_share<T>(RW * TC)));
   const int y0 = blk * RW;
@@ -366,7 +418,7 @@ __global__ __launch_bounds__((RW / 2) * (NX / row_elems<T, NX>()), (min_waves<T,
     stage_twiddles<T, NX, E>(twl, twg, tid, blockDim.x);
   }
 
-  if constexpr (MODE == ROW_SWEEP || MODE == ROW_C2R) {
+  if constexpr (SW || MODE == ROW_C2R) {
     for (int e = tid * EPC; e < SUB; e += blockDim.x * EPC) {
       const int g = e / (RW * TC), w = e - g * (RW * TC);
       const int rr = w / TC, cc = w - rr * TC;
@@ -428,9 +480,16 @@ __global__ __launch_bounds__((RW / 2) * (NX / row_elems<T, NX>()), (min_waves<T,
 #pragma unroll
         for (int q = 0; q < QB; ++q) {
           const T d1a = reg[h + q].re * sc, d1b = reg[h + q].im * sc;
-          reg[h + q] = cx<T>{white_update<T>(dv0[q], nb0[q], d1a, lt),
-                             white_update<T>(dv1[q], nb1[q], d1b, lt)};
+          const T t2a = white_update<T>(dv0[q], nb0[q], d1a, lt);
+          const T t2b = white_update<T>(dv1[q], nb1[q], d1b, lt);
+          if constexpr (JV) {
+            if (jdo) jacc += white_term<T>(dv0[q], nb0[q], t2a) + white_term<T>(dv1[q], nb1[q], t2b);
+          }
+          reg[h + q] = cx<T>{t2a, t2b};
         }
+      }
+      if constexpr (JV) {
+        if (jdo) wave_partial(jacc, jsh);
       }
     }
   } else {  // ROW_R2C
@@ -446,6 +505,9 @@ __global__ __launch_bounds__((RW / 2) * (NX / row_elems<T, NX>()), (min_waves<T,
 #pragma unroll
   for (int q = 0; q < E; ++q) lds[p * XS + LM::at(t + NT * q)] = reg[q];
   __syncthreads();
+  if constexpr (JV) {
+    if (jdo && tid == 0) gmem(a.jpart)[blk] = sum_partials(jsh, blockDim.x);
+  }
   // split Z into the two rows' spectra; write this block's rows, tile order
   for (int e = tid * EPC; e < SUB; e += blockDim.x * EPC) {
     cx<T> v[EPC];
@@ -473,9 +535,14 @@ __global__ __launch_bounds__((RW / 2) * (NX / row_elems<T, NX>()), (min_waves<T,
 // ---------------------------------------------------------------------------
 // column kernel: forward column FFT -> Fourier-side chain -> inverse FFT
 // ---------------------------------------------------------------------------
+// [wa a + wb b] / (wa + wb) with inv = 1 / (wa + wb).  The weights are
+// normalised before they touch the fields: a projected mode's covariance
+// (kInfiniteCov) times an unnormalised Fourier coefficient would overflow
+// float32, while wa * inv stays in [0, 1].
 template <class T>
 __device__ __forceinline__ cx<T> wavg(T wa, cx<T> a, T wb, cx<T> b, T inv) {
-  return cx<T>{(wa * a.re + wb * b.re) * inv, (wa * a.im + wb * b.im) * inv};
+  const T ua = wa * inv, ub = wb * inv;
+  return cx<T>{ua * a.re + ub * b.re, ua * a.im + ub * b.im};
 }
 
 // Per-mode coefficients of the chain at one sweep.
@@ -484,17 +551,33 @@ struct ChainCoef {
   T TW, TA, TB, SA, cB, nxr;
   int fk;
   bool store_first;
+  double jTW, jTA, jTB;  // lambda tau in float64, for the joint objective
 };
 
+template <class T>
+__device__ __forceinline__ double cnorm2(cx<T> a) {
+  const double r = a.re, i = a.im;
+  return r * r + i * i;
+}
+template <class T>
+__device__ __forceinline__ double cdist2(cx<T> a, cx<T> b) {
+  const double r = (double)a.re - (double)b.re, i = (double)a.im - (double)b.im;
+  return r * r + i * i;
+}
+
 // One mode: t_2 (white messenger, Fourier) in, field for the white level out.
-// Reads and writes the stored Fourier-side fields of this mode.
-template <class T, int FK>
+// Reads and writes the stored Fourier-side fields of this mode.  With JV, adds
+// jw times this mode's terms of the joint objective (unnormalised
+// coefficients; the caller applies 1/(nx ny)) to jacc.
+template <class T, int FK, bool JV>
 __device__ __forceinline__ cx<T> chain_mode(WF_GLOBAL cx<T>* tA, WF_GLOBAL cx<T>* dA,
                                             WF_GLOBAL cx<T>* tB, const ChainCoef<T>& k, int kx,
                                             int ky, size_t idx, cx<T> t2, T s, T nbA, T pst,
-                                            cx<T> tAo, cx<T> dAo, cx<T> tBo) {
+                                            cx<T> tAo, cx<T> dAo, cx<T> tBo, double& jacc,
+                                            double jw) {
   if constexpr (FK == FK_NONE) {
     if (k.store_first) stc(tA + idx, t2);
+    if constexpr (JV) jacc += jw * cnorm2(t2) / ((double)s + k.jTW);
     return cscale(t2, s / (s + k.TW));
   } else if constexpr (FK == FK_ARRAY_STRIPE) {
     const T nbB = (kx == 0 ? k.nxr * pst : (T)0) + k.cB;
@@ -506,6 +589,10 @@ __device__ __forceinline__ cx<T> chain_mode(WF_GLOBAL cx<T>* tA, WF_GLOBAL cx<T>
     stc(tB + idx, tBn);
     stc(dA + idx, dAn);
     stc(tA + idx, tAn);
+    if constexpr (JV)
+      jacc += jw * (cnorm2(tAn) / ((double)s + k.jTA) + cdist2(dAn, tAn) / (double)nbA +
+                     cdist2(tBn, dAn) / k.jTB + cdist2(dBn, tBn) / (double)nbB +
+                     cdist2(t2, dBn) / k.jTW);
     return dBn;
   } else {
     // one Fourier level: an array level or the stripe level
@@ -516,6 +603,9 @@ __device__ __forceinline__ cx<T> chain_mode(WF_GLOBAL cx<T>* tA, WF_GLOBAL cx<T>
     const cx<T> so = cscale(tAo, s / (s + k.SA));
     const cx<T> tAn = wavg(k.TA, dAn, nb, so, (T)1 / (nb + k.TA));
     stc(tA + idx, tAn);
+    if constexpr (JV)
+      jacc += jw * (cnorm2(tAn) / ((double)s + k.jTA) + cdist2(dAn, tAn) / (double)nb +
+                     cdist2(t2, dAn) / k.jTW);
     return dAn;
   }
 }
@@ -537,9 +627,13 @@ __global__ __launch_bounds__(TC * (NY / col_elems<T, NY>()), (col_min_waves<T, N
   constexpr bool LTW = lds_twiddles<T, NY>();
   __shared__ cx<T> twl[LTW ? NY : 1];
 
+  constexpr bool SW = MODE == COL_SWEEP || MODE == COL_SWEEP_J;
+  constexpr bool JV = MODE == COL_SWEEP_J;
+  __shared__ double jsh[JV ? 16 : 1];
+  double jacc = 0.0;
   double lam = 0.0, lamp = 0.0;
-  bool store_first = false;
-  if constexpr (MODE == COL_SWEEP) {
+  bool store_first = false;  // the chunk's last sweep (also: sum J there)
+  if constexpr (SW) {
     const WF_GLOBAL DevSched* s = gmem(a.sch);
     if (s->done) return;
     const int base = s->base;
@@ -685,7 +779,7 @@ __global__ __launch_bounds__(TC * (NY / col_elems<T, NY>()), (col_min_waves<T, N
     return;
   }
 
-  if constexpr (MODE == COL_SWEEP) {
+  if constexpr (SW) {
     ChainCoef<T> k;
     k.TW = (T)(lam * a.tauW);
     k.TA = (T)(lam * a.tauA);
@@ -695,6 +789,11 @@ __global__ __launch_bounds__(TC * (NY / col_elems<T, NY>()), (col_min_waves<T, N
     k.nxr = (T)a.nx;
     k.fk = a.fk;
     k.store_first = store_first;
+    k.jTW = lam * a.tauW;
+    k.jTA = lam * a.tauA;
+    k.jTB = lam * a.tauB;
+    // J only on the chunk's last sweep (block-uniform)
+    const bool jdo = JV && store_first;
     const cx<T> z = {(T)0, (T)0};
     if (!packed) {
       // this column, in batches of loads
@@ -705,8 +804,13 @@ __global__ __launch_bounds__(TC * (NY / col_elems<T, NY>()), (col_min_waves<T, N
         for (int q = 0; q < HB; ++q) {
           const int ky = t + NT * (h + q);
           const size_t idx = (size_t)kxc * NY + ky;
-          reg[h + q] = chain_mode<T, FK>(gtA, gdA, gtB, k, kxc, ky, idx, reg[h + q], sv[q], nv[q],
-                                         pv[q], ta[q], da[q], tb[q]);
+          if (jdo)
+            reg[h + q] = chain_mode<T, FK, JV>(gtA, gdA, gtB, k, kxc, ky, idx, reg[h + q], sv[q],
+                                               nv[q], pv[q], ta[q], da[q], tb[q], jacc, 2.0);
+          else
+            reg[h + q] = chain_mode<T, FK, false>(gtA, gdA, gtB, k, kxc, ky, idx, reg[h + q],
+                                                  sv[q], nv[q], pv[q], ta[q], da[q], tb[q], jacc,
+                                                  0.0);
         }
       }
     }
@@ -726,12 +830,17 @@ __global__ __launch_bounds__(TC * (NY / col_elems<T, NY>()), (col_min_waves<T, N
           const int li = LM::at(ky);
           const T ps = needP ? gps[ky] : (T)0;
           const size_t i0 = (size_t)ky, iN = (size_t)kxn * NY + ky;
-          reg[q] = chain_mode<T, FK>(gtA, gdA, gtB, k, 0, ky, i0, reg[q], gsc[i0],
-                                     needNb ? gnb[i0] : (T)0, ps, hasA ? ldc(gtA + i0) : z,
-                                     hasB ? ldc(gdA + i0) : z, hasB ? ldc(gtB + i0) : z);
-          cnl[li] = chain_mode<T, FK>(gtA, gdA, gtB, k, kxn, ky, iN, cnl[li], gsc[iN],
-                                      needNb ? gnb[iN] : (T)0, ps, hasA ? ldc(gtA + iN) : z,
-                                      hasB ? ldc(gdA + iN) : z, hasB ? ldc(gtB + iN) : z);
+          // k_y and NY - k_y of a real column are one conjugate pair; the
+          // terms are summed (weight > 0) on the chunk's last sweep only
+          const double jw = !jdo ? 0.0 : ((ky == 0 || ky == NY / 2) ? 1.0 : 2.0);
+          reg[q] = chain_mode<T, FK, JV>(gtA, gdA, gtB, k, 0, ky, i0, reg[q], gsc[i0],
+                                         needNb ? gnb[i0] : (T)0, ps, hasA ? ldc(gtA + i0) : z,
+                                         hasB ? ldc(gdA + i0) : z, hasB ? ldc(gtB + i0) : z,
+                                         jacc, jw);
+          cnl[li] = chain_mode<T, FK, JV>(gtA, gdA, gtB, k, kxn, ky, iN, cnl[li], gsc[iN],
+                                          needNb ? gnb[iN] : (T)0, ps, hasA ? ldc(gtA + iN) : z,
+                                          hasB ? ldc(gdA + iN) : z, hasB ? ldc(gtB + iN) : z,
+                                          jacc, jw);
           // C0 of k_y in (0, NY/2) waits in the unused CN slot of NY - k_y
           if (q < EH && ky > 0) cnl[LM::at(NY - ky)] = reg[q];
         }
@@ -792,8 +901,16 @@ __global__ __launch_bounds__(TC * (NY / col_elems<T, NY>()), (col_min_waves<T, N
     }
   }
 
+  if constexpr (JV) {
+    if (store_first) wave_partial(jacc, jsh);
+  }
   // the inverse transform reuses column 0's LDS region
   __syncthreads();
+  if constexpr (JV) {
+    // this block's share of the Fourier-side terms, unitary normalisation
+    if (store_first && tid == 0)
+      gmem(a.jpart)[a.jrow + g] = sum_partials(jsh, blockDim.x) * a.scale;
+  }
   if constexpr (LTW) fft<T, NY, true, E, true>(reg, lds + c * YS, t, (const cx<T>*)twl);
   else fft<T, NY, true, E, false>(reg, lds + c * YS, t, twg);
 #pragma unroll
@@ -994,6 +1111,7 @@ __global__ __launch_bounds__(256) void scale_kernel(T* __restrict__ x, int64_t n
     x[i] = (T)((double)x[i] * f);
 }
 
+#if WF_PART & 1
 // One block: fixed-order reduction of the monitor partials, then the cooling
 // schedule (fixed array, or the plateau rule of Section 3.3) and the stop test.
 __global__ __launch_bounds__(256) void controller_kernel(const CtrlArgs* __restrict__ argv) {
@@ -1006,30 +1124,35 @@ __global__ __launch_bounds__(256) void controller_kernel(const CtrlArgs* __restr
   double* __restrict__ trace = ca.trace;
   __shared__ double sh[16];
   if (s->done) return;
-  double a = 0.0, b = 0.0;
+  double a = 0.0, b = 0.0, jv = 0.0;
   for (int i = threadIdx.x; i < nblk; i += blockDim.x) {
     a += part[2 * i];
     b += part[2 * i + 1];
   }
+  for (int i = threadIdx.x; i < ca.njblk; i += blockDim.x) jv += ca.jpart[i];
   a = block_reduce<RED_SUM>(a, sh);
   b = block_reduce<RED_SUM>(b, sh);
+  jv = block_reduce<RED_SUM>(jv, sh);
   if (threadIdx.x != 0) return;
   const int klast = min(s->base + s->K, s->max_sweeps) - 1;
   const double l = lam[klast];
   const double rho = sqrt(a / s->d2);
   const double rho_mask = s->nu * sqrt(b) / sqrt(s->d2);
   if (s->n_rec < s->max_rec) {
-    double* r = trace + 5 * s->n_rec;
+    double* r = trace + kTraceCols * s->n_rec;
     r[0] = (double)klast;
     r[1] = l;
     r[2] = rho;
     r[3] = a;
     r[4] = rho_mask;
+    r[5] = jv;
     s->n_rec = s->n_rec + 1;
   }
   s->rho = rho;
   s->rho_mask = rho_mask;
   s->dd2 = a;
+  s->masked_x = sqrt(b);
+  s->J = jv;
   s->lam_last = l;
   s->sweeps_done = klast + 1;
   const double test = s->stop_full ? hypot(rho, rho_mask) : rho;
@@ -1056,6 +1179,7 @@ __global__ __launch_bounds__(256) void controller_kernel(const CtrlArgs* __restr
   }
   s->base = klast + 1;
 }
+#endif
 
 // ---------------------------------------------------------------------------
 // explicit instantiations and launch helpers (host-callable, C++ linkage)

@@ -20,8 +20,11 @@ enum FourierKind : int32_t {
   FK_ARRAY_STRIPE = 3,  // 1/f level (signal side) then the stripe level
 };
 
-enum RowMode : int32_t { ROW_SWEEP = 0, ROW_R2C = 1, ROW_C2R = 2 };
-enum ColMode : int32_t { COL_SWEEP = 0, COL_FWD_OUT = 1, COL_INV_IN = 2, COL_INIT = 3 };
+// ROW_SWEEP_J / COL_SWEEP_J: a sweep that also sums the joint objective's
+// terms (eqn 2mess_prob) when it is the last sweep of its chunk
+enum RowMode : int32_t { ROW_SWEEP = 0, ROW_R2C = 1, ROW_C2R = 2, ROW_SWEEP_J = 3 };
+enum ColMode : int32_t { COL_SWEEP = 0, COL_FWD_OUT = 1, COL_INV_IN = 2, COL_INIT = 3,
+                         COL_SWEEP_J = 4 };
 enum MonMode : int32_t { MON_RESIDUAL = 0, MON_OUTPUT = 1 };
 
 // Schedule state resident on the device.  Sweep kernels read it; only the
@@ -44,6 +47,8 @@ struct DevSched {
   double nu;           // largest observed white variance
   double dd2_prev;
   double rho, rho_mask, dd2, lam_last;
+  double masked_x;     // |(1 - m) x| at the last check
+  double J;            // joint objective J_lambda at the last check
 };
 
 template <class T>
@@ -67,14 +72,17 @@ struct SweepArgs {
   double cB;              // Nbar offset of a stripe level (phi - tau)
   double scale;           // 1 / (nx ny)
   int32_t warm_chain;     // warm start gives the chain's signal-end field itself
+  int32_t jrow;           // row-kernel blocks: column partials of J start there
+  double* jpart;          // per-block partial sums of the joint objective
 };
 
 // per-mode coefficient preparation (see prep_spectra_kernel)
 // An infinite noise variance on a Fourier mode (a 1/f spectrum entry of
 // +inf) projects that mode out of the data (Section 4).  It is carried as
 // this finite value: every update of the multiplied form then takes its
-// limit up to a relative 1e-30 * (largest other covariance), and every
-// product stays finite in float32.
+// limit up to a relative 1e-30 * (largest other covariance).  The sweep
+// normalises each pair of weights before multiplying a field by it, so no
+// product of this value with a field is formed.
 constexpr double kInfiniteCov = 1.0e30;
 
 struct PrepSpecArgs {
@@ -115,7 +123,12 @@ struct CtrlArgs {
   double* lam;
   const double* part;
   int nblk;
-  double* trace;
+  double* trace;       // kTraceCols values per monitor record
+  const double* jpart; // joint-objective partials of the chunk's last sweep
+  int njblk;
 };
+
+// columns of a trace record: sweep, lambda, rho, dd2, rho_mask, J
+constexpr int kTraceCols = 6;
 
 }  // namespace wf

@@ -49,6 +49,7 @@ struct Ctx {
   void* Mx = nullptr;  // monitor transit, context precision
   void* My = nullptr;
   double* part = nullptr;
+  double* jpart = nullptr;   // joint-objective partials (row blocks, then column blocks)
   double* stats = nullptr;
   DevSched* sch = nullptr;
   double* lam = nullptr;
@@ -106,7 +107,7 @@ void make_table(std::vector<T>& out, int n) {
 
 void free_ctx(Ctx* c) {
   void* bufs[] = {c->B, c->tA, c->dA, c->tB, c->sc, c->nbA, c->sy, c->sig, c->nbar2, c->twx, c->twy,
-                  c->Mx, c->My, c->part, c->stats, c->sch, c->lam, c->trace,
+                  c->Mx, c->My, c->part, c->jpart, c->stats, c->sch, c->lam, c->trace,
                   c->alpha_sk, c->d_args, c->d_margs, c->d_ctrl};
   for (void* p : bufs)
     if (p) (void)hipFree(p);
@@ -164,6 +165,9 @@ wf_status create(const wf_shape* sh, Ctx** out) {
   A(c->My, ny * c->kpm * 2 * esz);
   const size_t npart = std::max<size_t>(2 * ny / kTRM, 16 * kStatBlocks);
   A(c->part, npart * sizeof(double));
+  // at most ny/2 row blocks and nx/4 column blocks (every tiling has at
+  // least 2 rows per row block and 2 columns per tile)
+  A(c->jpart, (ny / 2 + nx / 4) * sizeof(double));
   A(c->stats, 16 * sizeof(double));
   A(c->sch, sizeof(DevSched));
   A(c->d_args, sizeof(SweepArgs<double>));
@@ -303,7 +307,22 @@ SweepArgs<T> sweep_args(Ctx* c, const wf_inputs* in, const Chain& ch) {
   a.tauW = ch.tauW;
   a.cB = ch.cB;
   a.scale = 1.0 / ((double)c->nx * (double)c->ny);
+  a.jrow = c->ny / kTiles[c->tile].RW;
+  a.jpart = c->jpart;
   return a;
+}
+
+// joint-objective partials of one sweep: row blocks, then column blocks
+int j_blocks(const Ctx* c) {
+  const TileCfg& t = kTiles[c->tile];
+  return c->ny / t.RW + (c->nx / 2) / t.TC;
+}
+
+// Sweeps launched with the joint-objective variants: those that can close a
+// chunk (the last of a full chunk, and the last of the budget when the
+// budget is not a multiple of K).  They sum J only when they do.
+bool j_sweep(int k, int K, int max_sweeps) {
+  return k == K - 1 || k == (max_sweeps - 1) % K;
 }
 
 template <class T>
@@ -432,7 +451,7 @@ wf_status map_setup(Ctx* c, const wf_inputs* in, const wf_schedule* s, const voi
     if (c->trace) (void)hipFree(c->trace);
     c->trace = nullptr;
     c->trace_cap = 0;
-    wf_status as = alloc((void**)&c->trace, (size_t)r.n_chunks * 5 * sizeof(double));
+    wf_status as = alloc((void**)&c->trace, (size_t)r.n_chunks * kTraceCols * sizeof(double));
     if (as != WF_OK) return as;
     c->trace_cap = r.n_chunks;
   }
@@ -464,7 +483,7 @@ wf_status map_setup(Ctx* c, const wf_inputs* in, const wf_schedule* s, const voi
   r.m.sch = dsched;
   r.m.s_out = s_out;
   r.m.out_chain = s->field_mode;
-  r.ctrl = CtrlArgs{dsched, c->lam, c->part, c->ny / kTRM, c->trace};
+  r.ctrl = CtrlArgs{dsched, c->lam, c->part, c->ny / kTRM, c->trace, c->jpart, j_blocks(c)};
   // initial state (the single-map argument block is used for the warm start)
   const size_t modes_b = (size_t)c->nh * c->ny * 2 * c->esz;
   if (s_init) {
@@ -497,10 +516,11 @@ wf_status enqueue_chunk(std::vector<ShapeClass<T>>& cls, const std::vector<MapRu
       const SweepArgs<T>& a0 = runs[cls[i].maps[0]].a;
       const int n = (int)cls[i].maps.size();
       const bool timed = ev && k == 0 && i == 0;
-      WF_TRY(launch_row<T>(cls[i].tile, ROW_SWEEP, a0, cls[i].argv, n, k, nullptr, nullptr, st,
-                           timed ? ev[0] : nullptr, timed ? ev[1] : nullptr));
-      WF_TRY(launch_col<T>(cls[i].tile, COL_SWEEP, a0, cls[i].argv, n, k, nullptr, 0.0, st,
-                           timed ? ev[2] : nullptr, timed ? ev[3] : nullptr));
+      const bool jv = j_sweep(k, K, runs[cls[i].maps[0]].h.max_sweeps);
+      WF_TRY(launch_row<T>(cls[i].tile, jv ? ROW_SWEEP_J : ROW_SWEEP, a0, cls[i].argv, n, k,
+                           nullptr, nullptr, st, timed ? ev[0] : nullptr, timed ? ev[1] : nullptr));
+      WF_TRY(launch_col<T>(cls[i].tile, jv ? COL_SWEEP_J : COL_SWEEP, a0, cls[i].argv, n, k,
+                           nullptr, 0.0, st, timed ? ev[2] : nullptr, timed ? ev[3] : nullptr));
     }
   }
   if (ev) WF_TRY(hipEventRecord(ev[4], st));
@@ -521,9 +541,13 @@ wf_status enqueue_class(ShapeClass<T>& cl, const std::vector<MapRun<T>>& runs, i
   const SweepArgs<T>& a0 = runs[cl.maps[0]].a;
   const MonArgs<T>& m0 = runs[cl.maps[0]].m;
   const int n = (int)cl.maps.size();
+  const int maxs = runs[cl.maps[0]].h.max_sweeps;
   for (int k = 0; k < K; ++k) {
-    WF_TRY(launch_row<T>(cl.tile, ROW_SWEEP, a0, cl.argv, n, k, nullptr, nullptr, st));
-    WF_TRY(launch_col<T>(cl.tile, COL_SWEEP, a0, cl.argv, n, k, nullptr, 0.0, st));
+    const bool jv = j_sweep(k, K, maxs);
+    WF_TRY(launch_row<T>(cl.tile, jv ? ROW_SWEEP_J : ROW_SWEEP, a0, cl.argv, n, k, nullptr,
+                         nullptr, st));
+    WF_TRY(launch_col<T>(cl.tile, jv ? COL_SWEEP_J : COL_SWEEP, a0, cl.argv, n, k, nullptr, 0.0,
+                         st));
   }
   WF_TRY(launch_mon_col<T>(m0, cl.margv, n, MON_RESIDUAL, st));
   WF_TRY(launch_mon_row<T>(m0, cl.margv, n, MON_RESIDUAL, st));
@@ -541,6 +565,8 @@ void fill_report(wf_report* rep, const DevSched& fin, const Chain& ch, const dou
   rep->rho_mask = fin.rho_mask;
   rep->dd2 = fin.dd2;
   rep->d2 = pix[3];
+  rep->chi2_joint = fin.J;
+  rep->masked_x_norm = fin.masked_x;
   for (int i = 0; i < 3; ++i) rep->tau[i] = ch.tau_report[i];
   rep->phi = ch.phi;
 }
@@ -600,7 +626,7 @@ wf_status solve_t(Ctx* c, const wf_inputs* in, const wf_schedule* s, const void*
   WF_TRY(launch_mon_col<T>(r.m, cls[0].margv, 1, MON_OUTPUT, st));
   WF_TRY(launch_mon_row<T>(r.m, cls[0].margv, 1, MON_OUTPUT, st));
   if (trace && fin.n_rec > 0)
-    WF_TRY(hipMemcpyAsync(trace, c->trace, (size_t)fin.n_rec * 5 * sizeof(double),
+    WF_TRY(hipMemcpyAsync(trace, c->trace, (size_t)fin.n_rec * kTraceCols * sizeof(double),
                           hipMemcpyDeviceToHost, st));
   WF_TRY(hipStreamSynchronize(st));
 

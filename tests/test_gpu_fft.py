@@ -6,8 +6,8 @@ import pytest
 
 pytestmark = pytest.mark.gpu
 
-SHAPES = [(64, 64), (128, 64), (64, 256), (512, 512), (2048, 2048), (256, 4096),
-          (384, 384), (768, 256), (128, 1536), (1536, 768)]
+SHAPES = [(64, 64), (128, 64), (64, 256), (512, 512), (1024, 1024), (2048, 2048), (256, 4096),
+          (4096, 256), (384, 384), (768, 256), (128, 1536), (1536, 768)]
 
 
 def _tol(prec, n):

@@ -188,6 +188,47 @@ def test_adaptive_schedule_replayed_by_oracle(gpu_lib, prec):
     assert _rel(s_gpu.cpu().numpy().astype(np.float64), res.s) < TOL[prec]
 
 
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_adaptive_decisions_follow_the_section_3_3_rule(gpu_lib, prec):
+    """The device controller's cooling decisions, replayed on the host from
+    the residuals the GPU itself recorded through oracle.next_lambda (the
+    rule pinned on hand-built sequences): every lambda in the trace is the
+    rule's output after the previous check."""
+    p = synth.make_problem(128, 128, 14, mask_frac=0.05)
+    ctx = gpu_lib.Context(128, 128, prec)
+    K = 4
+    sched = gpu_lib.Schedule(lambda0=1e4, shrink=0.7, plateau=3e-2, rtol=0.0, max_sweeps=600,
+                             monitor_every=K, chain="augmented")
+    _, rep, trace = ctx.solve(*_tensors(p, prec), schedule=sched)
+    rule = oracle.AdaptiveSchedule(lam0=1e4, shrink=0.7, plateau=3e-2, snap=1e-3)
+    lam, prev = 1e4, None
+    shrinks = 0
+    for i, row in enumerate(trace):
+        assert row[1] == pytest.approx(lam, rel=1e-14), i
+        new, prev = oracle.next_lambda(rule, lam, prev, int(row[0]), row[3])
+        shrinks += new < lam
+        lam = new
+    assert shrinks >= 5
+
+
+@pytest.mark.parametrize("chain", ["merged", "three"])
+def test_projected_modes_float32_full_size(gpu_lib, chain):
+    """Projected modes (1/f variance +inf, carried as 1e30) on the 2048^2 map
+    in float32: the sweep forms normalised weights before touching a field,
+    so no product overflows (unnormalised low-k coefficients reach 2e8)."""
+    import dataclasses
+    oracle.bases.set_workers(16)
+    p = synth.named_config("c3")
+    po = np.array(p.p_oof)
+    for ky in (0, 1, 2, 2046, 2047):
+        po[ky, :3] = np.inf
+    p = dataclasses.replace(p, p_oof=po)
+    lams = [1e4, 3e3, 1e3]
+    s_gpu, rep, trace, res = _run_both(gpu_lib, p, "f32", lams, chain=chain, monitor_every=3)
+    assert np.all(np.isfinite(s_gpu))
+    assert _rel(s_gpu, res.s) < TOL["f32"]
+
+
 def test_converges_to_dense_wiener_solution_f64(gpu_lib):
     """C1 workload (64x64, three terms) on the float64 path with the
     augmented chain, run to rho <= 1e-12 and compared with the dense
