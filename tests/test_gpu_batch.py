@@ -15,7 +15,7 @@ import synth
 
 pytestmark = pytest.mark.gpu
 
-TOL = {"f32": 1e-5, "f64": 1e-10}
+from parity_checks import TOL, assert_parity
 
 
 def _dict(p, prec):
@@ -82,7 +82,7 @@ def test_batch_fixed_schedule_matches_single_and_oracle(gpu_lib, prec, chain):
         res = oracle.solve(probs[i], oracle.FixedSchedule(lams),
                            settings=oracle.Settings(chain=chain), max_sweeps=len(lams),
                            monitor_every=4)
-        assert _rel(outs[i].astype(np.float64), res.s) < TOL[prec]
+        assert_parity(outs[i].astype(np.float64), res.s, prec)
 
 
 @pytest.mark.parametrize("prec", ["f64", "f32"])
@@ -162,7 +162,7 @@ def test_uneven_batch_shapes(gpu_lib):
         assert np.array_equal(outs[i], s1), i
     res = oracle.solve(probs[3], oracle.FixedSchedule(lams), max_sweeps=len(lams),
                        monitor_every=8)
-    assert _rel(outs[3].astype(np.float64), res.s) < TOL["f32"]
+    assert_parity(outs[3].astype(np.float64), res.s, "f32")
 
 
 @pytest.mark.parametrize("prec", ["f64", "f32"])

@@ -8,7 +8,7 @@ import synth
 
 pytestmark = pytest.mark.gpu
 
-TOL = {"f32": 1e-5, "f64": 1e-10}
+from parity_checks import TOL, assert_parity
 
 
 def _t(a, prec, torch):
@@ -35,7 +35,7 @@ def test_inverse_noise_weight_parity(gpu_lib, prec, chain):
                                       settings=oracle.Settings(chain=chain),
                                       max_sweeps=len(lams), monitor_every=10)
     got = out.cpu().numpy().astype(np.float64)
-    assert np.linalg.norm(got - ref.s) / np.linalg.norm(ref.s) < TOL[prec]
+    assert_parity(got, ref.s, prec)
 
 
 def test_inverse_noise_weight_converges_to_dense(gpu_lib):
