@@ -19,18 +19,18 @@ def assert_parity(s_gpu, ref, prec):
     norm, or of the share of the whole field's bar that falls on one column
     where the column is nearly empty."""
     tol = TOL[prec]
-    rel = rel(s_gpu, ref)
+    err = rel(s_gpu, ref)
     emax = float(np.max(np.abs(s_gpu - ref)) / np.max(np.abs(ref)))
     G, R = np.fft.rfft2(s_gpu), np.fft.rfft2(ref)
     nh = R.shape[1]
     cols = []
     for kx in (0, nh - 1):
-        err = float(np.linalg.norm(G[:, kx] - R[:, kx]))
+        col_err = float(np.linalg.norm(G[:, kx] - R[:, kx]))
         bound = max(10 * tol * np.linalg.norm(R[:, kx]), 10 * tol * np.linalg.norm(R) / np.sqrt(nh))
-        cols.append((kx, err, bound))
-    print(f"  rel L2 {rel:.2e}, max {emax:.2e}, columns " +
+        cols.append((kx, col_err, bound))
+    print(f"  rel L2 {err:.2e}, max {emax:.2e}, columns " +
           ", ".join(f"k_x={kx}: {e:.2e} (bound {b:.2e})" for kx, e, b in cols), flush=True)
-    assert rel < tol
+    assert err < tol
     assert emax < 5 * tol
     for kx, e, b in cols:
         assert e < b, kx
