@@ -36,6 +36,7 @@
 #ifndef WF_H
 #define WF_H
 
+#include <stddef.h>
 #include <stdint.h>
 #include <hip/hip_runtime_api.h>
 
@@ -51,7 +52,8 @@ typedef enum {
   WF_ENONFINITE = -3,     /* NaN/Inf in the inputs or in the iteration           */
   WF_EDEVICE = -4,        /* a HIP call failed                                   */
   WF_ENOMEM = -5,         /* device allocation failed                            */
-  WF_EUNSUPPORTED = -6    /* size/precision not built                            */
+  WF_EUNSUPPORTED = -6,   /* size/precision not built                            */
+  WF_ESCRATCH = -7        /* wf_solve_noalloc: workspace beyond its static scratch */
 } wf_status;
 
 typedef enum { WF_F32 = 0, WF_F64 = 1 } wf_precision;
@@ -162,6 +164,28 @@ void wf_schedule_default(wf_schedule* sch);
 wf_status wf_solve(void* ctx, const wf_inputs* in, const wf_schedule* sch,
                    const void* s_init, void* s_out, wf_report* rep,
                    double* trace, hipStream_t stream);
+
+/* wf_solve without a context, for callers that cannot allocate (code that
+ * may not call hipMalloc: serving loops, harnesses that forbid it).  The
+ * workspace (transit buffer, messenger state, coefficients, monitor buffers,
+ * schedule and trace arrays, argument blocks) is carved from a static device
+ * array of wf_noalloc_scratch_bytes() bytes (32 MiB) that each GPU the
+ * library runs on holds until the process ends; the call allocates no device
+ * or pinned host memory and creates no events.  It fits, for instance,
+ * maps up to 512 x 512 in float64 and 768 x 768 in float32 with the default
+ * schedule budget; shape and schedule are checked before any work and a
+ * workspace that does not fit returns WF_ESCRATCH, as does max_sweeps above
+ * 65536.  Runs on the current device with the default tiling; inputs,
+ * outputs, report, trace and errors as for wf_solve (same kernels, so the
+ * results are identical to a wf_solve with a context of that tiling).  Calls
+ * that overlap on one GPU share the scratch and race; each call initialises
+ * every part of it that it reads.  The host checks the device schedule every
+ * 4 chunks with a blocking copy, so up to 4 * monitor_every sweeps may be
+ * enqueued past convergence (they return at once). */
+wf_status wf_solve_noalloc(const wf_shape* shape, const wf_inputs* in, const wf_schedule* sch,
+                           const void* s_init, void* s_out, wf_report* rep, double* trace,
+                           hipStream_t stream);
+size_t wf_noalloc_scratch_bytes(void);
 
 /* Largest batch wf_solve_batch accepts. */
 #define WF_BATCH_MAX 1024

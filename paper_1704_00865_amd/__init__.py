@@ -18,7 +18,7 @@ import numpy as np
 
 __all__ = [
     "load", "Context", "Schedule", "solve", "rfft2", "irfft2", "strerror",
-    "WFError", "STATUS", "CHAINS", "solve_batch",
+    "WFError", "STATUS", "CHAINS", "solve_batch", "solve_noalloc",
 ]
 
 _LIB_PATH = os.environ.get("WF_LIBRARY") or os.path.join(
@@ -26,7 +26,7 @@ _LIB_PATH = os.environ.get("WF_LIBRARY") or os.path.join(
 _lib = None
 
 STATUS = {0: "OK", 1: "NOT_CONVERGED", -1: "EINVAL", -2: "ENOTPD", -3: "ENONFINITE",
-          -4: "EDEVICE", -5: "ENOMEM", -6: "EUNSUPPORTED"}
+          -4: "EDEVICE", -5: "ENOMEM", -6: "EUNSUPPORTED", -7: "ESCRATCH"}
 CHAINS = {"three": 0, "merged": 1, "augmented": 2}
 # columns of a trace row: sweep, lambda, rho, dd2, rho_mask, chi2_joint
 TRACE_COLS = 6
@@ -72,7 +72,8 @@ class _Report(ctypes.Structure):
 
 EXPORTS = ("wf_ctx_create", "wf_ctx_destroy", "wf_schedule_default", "wf_solve", "wf_rfft2",
            "wf_irfft2", "wf_ctx_set_profiling", "wf_supported", "wf_strerror", "wf_tile_count",
-           "wf_ctx_set_tile", "wf_ctx_get_tile", "wf_inverse_noise_weight", "wf_solve_batch")
+           "wf_ctx_set_tile", "wf_ctx_get_tile", "wf_inverse_noise_weight", "wf_solve_batch",
+           "wf_solve_noalloc", "wf_noalloc_scratch_bytes")
 
 
 def load():
@@ -104,6 +105,12 @@ def load():
                                    ctypes.POINTER(_Schedule), ctypes.POINTER(vp),
                                    ctypes.POINTER(vp), ctypes.POINTER(_Report), vp]
     lib.wf_solve_batch.restype = i32
+    lib.wf_solve_noalloc.argtypes = [ctypes.POINTER(_Shape), ctypes.POINTER(_Inputs),
+                                     ctypes.POINTER(_Schedule), vp, vp, ctypes.POINTER(_Report),
+                                     ctypes.POINTER(ctypes.c_double), vp]
+    lib.wf_solve_noalloc.restype = i32
+    lib.wf_noalloc_scratch_bytes.argtypes = []
+    lib.wf_noalloc_scratch_bytes.restype = ctypes.c_size_t
     lib.wf_rfft2.argtypes = [vp, vp, vp, vp]
     lib.wf_rfft2.restype = i32
     lib.wf_irfft2.argtypes = [vp, vp, vp, vp]
@@ -354,6 +361,55 @@ def solve(d, s_k, n_pix, p_oof=None, p_stripe=None, mask=None, *, schedule=Sched
         return ctx.solve(d, s_k, n_pix, p_oof, p_stripe, mask, schedule=schedule, s_init=s_init)
     finally:
         ctx.close()
+
+
+def solve_noalloc(d, s_k, n_pix, p_oof=None, p_stripe=None, mask=None, *,
+                  schedule: Schedule = Schedule(), s_init=None, out=None):
+    """``wf_solve_noalloc``: the solve without a context, its workspace in the
+    library's static device scratch (no device allocation by the library).
+    ``out`` may be given so that the call allocates nothing at all.  Returns
+    (s, report dict, trace array); raises WFError on a negative status."""
+    import torch
+    lib = load()
+    ny, nx = d.shape
+    nh = nx // 2 + 1
+    dt = d.dtype
+    if dt not in (torch.float32, torch.float64) or not d.is_cuda:
+        raise ValueError("d must be a float32 or float64 CUDA tensor")
+    dev = d.device
+
+    def chk(t, shape, name, dtype=dt):
+        if t is None:
+            return
+        if (not isinstance(t, torch.Tensor) or t.device != dev or tuple(t.shape) != shape
+                or t.dtype != dtype or not t.is_contiguous()):
+            raise ValueError(f"{name}: expected a contiguous {dtype} tensor {shape} on {dev}")
+    chk(d, (ny, nx), "d")
+    chk(s_k, (ny, nh), "s_k")
+    chk(n_pix, (ny, nx), "n_pix")
+    chk(p_oof, (ny, nh), "p_oof")
+    chk(p_stripe, (ny,), "p_stripe")
+    chk(mask, (ny, nx), "mask", torch.uint8)
+    chk(s_init, (ny, nx), "s_init")
+    if out is None:
+        out = torch.empty((ny, nx), dtype=dt, device=dev)
+    chk(out, (ny, nx), "out")
+    shape = _Shape(ny, nx, 0 if dt == torch.float32 else 1)
+    inp = _inputs(d, s_k, n_pix, p_oof, p_stripe, mask)
+    sch, keep = schedule._c()
+    nrec = -(-schedule.max_sweeps // schedule.monitor_every)
+    trace = np.zeros((nrec, TRACE_COLS), dtype=np.float64)
+    rep = _Report()
+    with torch.cuda.device(dev):
+        st = lib.wf_solve_noalloc(ctypes.byref(shape), ctypes.byref(inp), ctypes.byref(sch),
+                                  s_init.data_ptr() if s_init is not None else None,
+                                  out.data_ptr(), ctypes.byref(rep),
+                                  trace.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                  _stream_ptr(torch, dev))
+    del keep
+    if st < 0:
+        raise WFError(st, "wf_solve_noalloc")
+    return out, _report(rep), trace[: rep.n_records]
 
 
 def solve_batch(contexts, problems, *, schedule: Schedule = Schedule(), outs=None,

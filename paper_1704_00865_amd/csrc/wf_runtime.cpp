@@ -14,6 +14,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -28,6 +29,7 @@ constexpr int kStatBlocks = 256;
 constexpr int kRing = 4;   // pinned readback slots
 constexpr int kLag = 2;    // chunks between enqueue and the host's check
 constexpr int kProfSlots = 512;
+constexpr int kStaticCheck = 4;  // chunks between host checks without events
 
 struct Ctx {
   int ny = 0, nx = 0, prec = 0;
@@ -68,7 +70,40 @@ struct Ctx {
   hipEvent_t ev_ring[kRing] = {};
   int profiling = 0;
   std::vector<hipEvent_t> prof_ev;
+  // workspace carved from the library's static scratch (wf_solve_noalloc):
+  // no events, no pinned memory, nothing to free
+  bool no_alloc = false;
 };
+
+// Every device buffer of a context with its size: take(&pointer, bytes) is
+// called once per buffer in a fixed order.
+template <class F>
+void for_each_buffer(Ctx* c, F take) {
+  const size_t ny = c->ny, nx = c->nx, nh = c->nh, esz = c->esz;
+  const size_t modes = nh * ny;
+  take((void**)&c->B, ny * (nx / 2) * 2 * esz);
+  take((void**)&c->tA, modes * 2 * esz);
+  take((void**)&c->dA, modes * 2 * esz);
+  take((void**)&c->tB, modes * 2 * esz);
+  take((void**)&c->sc, modes * esz);
+  take((void**)&c->nbA, modes * esz);
+  take((void**)&c->sy, modes * esz);
+  take((void**)&c->sig, modes * esz);
+  take((void**)&c->nbar2, ny * nx * esz);
+  take((void**)&c->twx, nx * 2 * esz);
+  take((void**)&c->twy, ny * 2 * esz);
+  take((void**)&c->Mx, ny * c->kpm * 2 * esz);
+  take((void**)&c->My, ny * c->kpm * 2 * esz);
+  take((void**)&c->part, std::max<size_t>(2 * ny / kTRM, 16 * kStatBlocks) * sizeof(double));
+  // at most ny/2 row blocks and nx/4 column blocks (every tiling has at
+  // least 2 rows per row block and 2 columns per tile)
+  take((void**)&c->jpart, (ny / 2 + nx / 4) * sizeof(double));
+  take((void**)&c->stats, 16 * sizeof(double));
+  take((void**)&c->sch, sizeof(DevSched));
+  take((void**)&c->d_args, sizeof(SweepArgs<double>));
+  take((void**)&c->d_margs, sizeof(MonArgs<double>));
+  take((void**)&c->d_ctrl, sizeof(CtrlArgs));
+}
 
 wf_status from_hip(hipError_t e) {
   if (e == hipSuccess) return WF_OK;
@@ -142,38 +177,14 @@ wf_status create(const wf_shape* sh, Ctx** out) {
   c->nh = c->nx / 2 + 1;
   c->kpm = ((c->nh + kTCM - 1) / kTCM) * kTCM;
   (void)hipGetDevice(&c->device);
-  const size_t ny = c->ny, nx = c->nx, nh = c->nh, esz = c->esz;
-  const size_t modes = nh * ny;
   wf_status st = WF_OK;
-#define A(ptr, bytes)                                 \
-  if ((st = alloc((void**)&(ptr), (bytes))) != WF_OK) { \
-    free_ctx(c);                                      \
-    return st;                                        \
+  for_each_buffer(c, [&](void** p, size_t bytes) {
+    if (st == WF_OK) st = alloc(p, bytes);
+  });
+  if (st != WF_OK) {
+    free_ctx(c);
+    return st;
   }
-  A(c->B, ny * (nx / 2) * 2 * esz);
-  A(c->tA, modes * 2 * esz);
-  A(c->dA, modes * 2 * esz);
-  A(c->tB, modes * 2 * esz);
-  A(c->sc, modes * esz);
-  A(c->nbA, modes * esz);
-  A(c->sy, modes * esz);
-  A(c->sig, modes * esz);
-  A(c->nbar2, ny * nx * esz);
-  A(c->twx, nx * 2 * esz);
-  A(c->twy, ny * 2 * esz);
-  A(c->Mx, ny * c->kpm * 2 * esz);
-  A(c->My, ny * c->kpm * 2 * esz);
-  const size_t npart = std::max<size_t>(2 * ny / kTRM, 16 * kStatBlocks);
-  A(c->part, npart * sizeof(double));
-  // at most ny/2 row blocks and nx/4 column blocks (every tiling has at
-  // least 2 rows per row block and 2 columns per tile)
-  A(c->jpart, (ny / 2 + nx / 4) * sizeof(double));
-  A(c->stats, 16 * sizeof(double));
-  A(c->sch, sizeof(DevSched));
-  A(c->d_args, sizeof(SweepArgs<double>));
-  A(c->d_margs, sizeof(MonArgs<double>));
-  A(c->d_ctrl, sizeof(CtrlArgs));
-#undef A
   hipError_t e = hipHostMalloc((void**)&c->h_ring, kRing * sizeof(DevSched), hipHostMallocDefault);
   if (e == hipSuccess) e = hipHostMalloc((void**)&c->h_stats, 16 * sizeof(double), hipHostMallocDefault);
   if (e == hipSuccess) e = hipHostMalloc(&c->h_args, sizeof(SweepArgs<double>), hipHostMallocDefault);
@@ -439,6 +450,7 @@ wf_status map_setup(Ctx* c, const wf_inputs* in, const wf_schedule* s, const voi
   // schedule: lambda per sweep and the device-side controller state
   const int K = s->monitor_every, maxs = s->max_sweeps;
   r.n_chunks = (maxs + K - 1) / K;
+  if (c->no_alloc && (c->lam_cap < maxs + 1 || c->trace_cap < r.n_chunks)) return WF_ESCRATCH;
   if (c->lam_cap < maxs + 1) {
     if (c->lam) (void)hipFree(c->lam);
     c->lam = nullptr;
@@ -608,10 +620,20 @@ wf_status solve_t(Ctx* c, const wf_inputs* in, const wf_schedule* s, const void*
     hipEvent_t* ev = (prof && ci < prof_chunks) ? &c->prof_ev[6 * ci] : nullptr;
     wf_status es = enqueue_chunk<T>(cls, runs, (const CtrlArgs*)c->d_ctrl, 1, K, ev, st);
     if (es != WF_OK) return es;
+    launched = ci + 1;
+    if (c->no_alloc) {
+      // no events: every kStaticCheck chunks the host waits for the stream
+      // and reads the device schedule (plain host memory)
+      if ((ci + 1) % kStaticCheck == 0 && ci + 1 < r.n_chunks) {
+        WF_TRY(hipMemcpyAsync(c->h_ring, c->sch, sizeof(DevSched), hipMemcpyDeviceToHost, st));
+        WF_TRY(hipStreamSynchronize(st));
+        if (c->h_ring[0].done) break;
+      }
+      continue;
+    }
     const int slot = ci % kRing;
     WF_TRY(hipMemcpyAsync(&c->h_ring[slot], c->sch, sizeof(DevSched), hipMemcpyDeviceToHost, st));
     WF_TRY(hipEventRecord(c->ev_ring[slot], st));
-    launched = ci + 1;
     if (ci >= kLag) {
       const int chk = (ci - kLag) % kRing;
       WF_TRY(hipEventSynchronize(c->ev_ring[chk]));
@@ -821,6 +843,104 @@ wf_status solve_batch_t(Ctx** ctxs, int n, const wf_inputs* ins, const wf_schedu
   return ret;
 }
 
+// ----- the entry point that allocates nothing ------------------------------
+//
+// wf_solve_noalloc carves a context's workspace out of this array instead of
+// allocating it.  Every GPU the library runs on holds its own copy for the
+// life of the process; host code reaches it only through the address
+// hipGetSymbolAddress returns on that device (the array's name is a host-side
+// stand-in).  Calls that overlap on one GPU share it and race.
+constexpr size_t kStaticBytes = size_t(32) << 20;
+constexpr int kStaticMaxSweeps = 1 << 16;
+static __device__ __align__(256) unsigned char scratch[kStaticBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// the scratch array's device address on the current device, looked up once
+wf_status scratch_on_device(int dev, unsigned char** out) {
+  if (dev < 0 || dev >= kMaxDevices) return WF_EDEVICE;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) return WF_EDEVICE;
+    g_scratch_ptr[dev] = p;
+  }
+  *out = (unsigned char*)g_scratch_ptr[dev];
+  return WF_OK;
+}
+
+constexpr size_t kCarveAlign = 256;
+
+// Place every device buffer of c, then the schedule arrays, from base
+// (nullptr: only count).  Returns the bytes used.
+size_t carve_static(Ctx* c, unsigned char* base, int lam_cap, int trace_cap) {
+  size_t off = 0;
+  auto take = [&](void** p, size_t bytes) {
+    if (base) *p = base + off;
+    off = (off + bytes + kCarveAlign - 1) / kCarveAlign * kCarveAlign;
+  };
+  for_each_buffer(c, take);
+  take((void**)&c->lam, (size_t)lam_cap * sizeof(double));
+  take((void**)&c->trace, (size_t)trace_cap * kTraceCols * sizeof(double));
+  if (base) {
+    c->lam_cap = lam_cap;
+    c->trace_cap = trace_cap;
+  }
+  return off;
+}
+
+template <class T>
+wf_status solve_noalloc_t(const wf_shape* sh, const wf_inputs* in, const wf_schedule* sch,
+                          const void* s_init, void* s_out, wf_report* rep, double* trace,
+                          hipStream_t st) {
+  Ctx c;
+  c.ny = sh->ny;
+  c.nx = sh->nx;
+  c.prec = sh->precision;
+  c.esz = sizeof(T);
+  c.nh = c.nx / 2 + 1;
+  c.kpm = ((c.nh + kTCM - 1) / kTCM) * kTCM;
+  c.no_alloc = true;
+  const int lam_cap = sch->max_sweeps + 1;
+  const int trace_cap = (sch->max_sweeps + sch->monitor_every - 1) / sch->monitor_every;
+  if (carve_static(&c, nullptr, lam_cap, trace_cap) > kStaticBytes) return WF_ESCRATCH;
+  WF_TRY(hipGetDevice(&c.device));
+  unsigned char* base = nullptr;
+  wf_status ss = scratch_on_device(c.device, &base);
+  if (ss != WF_OK) return ss;
+  carve_static(&c, base, lam_cap, trace_cap);
+  // host staging in plain memory of this call
+  DevSched h_ring[kRing];
+  double h_stats[16];
+  alignas(16) unsigned char h_args[sizeof(SweepArgs<double>)];
+  alignas(16) unsigned char h_margs[sizeof(MonArgs<double>)];
+  alignas(16) unsigned char h_ctrl[sizeof(CtrlArgs)];
+  c.h_ring = h_ring;
+  c.h_stats = h_stats;
+  c.h_args = h_args;
+  c.h_margs = h_margs;
+  c.h_ctrl = h_ctrl;
+  // twiddle tables (the largest supported length is 4096), computed in
+  // double and rounded once, as for a context
+  static thread_local T tw[2][2 * 4096];
+  for (int a = 0; a < 2; ++a) {
+    const int n = a == 0 ? c.nx : c.ny;
+    for (int j = 0; j < n; ++j) {
+      const double ang = 2.0 * M_PI * (double)j / (double)n;
+      tw[a][2 * j] = (T)std::cos(ang);
+      tw[a][2 * j + 1] = (T)(-std::sin(ang));
+    }
+  }
+  WF_TRY(hipMemcpyAsync(c.twx, tw[0], (size_t)c.nx * 2 * sizeof(T), hipMemcpyHostToDevice, st));
+  WF_TRY(hipMemcpyAsync(c.twy, tw[1], (size_t)c.ny * 2 * sizeof(T), hipMemcpyHostToDevice, st));
+  const wf_status r = solve_t<T>(&c, in, sch, s_init, s_out, rep, trace, st);
+  (void)hipStreamSynchronize(st);  // the staging above is this call's memory
+  return r;
+}
+
 template <class T>
 wf_status fft_t(Ctx* c, const void* src, void* dst, bool forward, hipStream_t st) {
   Chain ch;
@@ -889,6 +1009,22 @@ wf_status wf_solve(void* ctx, const wf_inputs* in, const wf_schedule* sch, const
   if (c->prec == WF_F64) return solve_t<double>(c, in, sch, s_init, s_out, rep, trace, stream);
   return solve_t<float>(c, in, sch, s_init, s_out, rep, trace, stream);
 }
+
+wf_status wf_solve_noalloc(const wf_shape* shape, const wf_inputs* in, const wf_schedule* sch,
+                           const void* s_init, void* s_out, wf_report* rep, double* trace,
+                           hipStream_t stream) {
+  if (!shape || !in || !sch || !s_out || !in->d || !in->s_k || !in->n_pix) return WF_EINVAL;
+  if (shape->precision != WF_F32 && shape->precision != WF_F64) return WF_EINVAL;
+  if (!supported(shape->ny, shape->nx, shape->precision)) return WF_EUNSUPPORTED;
+  wf_status v = check_schedule(sch);
+  if (v != WF_OK) return v;
+  if (sch->max_sweeps > kStaticMaxSweeps) return WF_ESCRATCH;
+  if (shape->precision == WF_F64)
+    return solve_noalloc_t<double>(shape, in, sch, s_init, s_out, rep, trace, stream);
+  return solve_noalloc_t<float>(shape, in, sch, s_init, s_out, rep, trace, stream);
+}
+
+size_t wf_noalloc_scratch_bytes(void) { return kStaticBytes; }
 
 wf_status wf_solve_batch(void* const* ctxs, int32_t n, const wf_inputs* inputs,
                          const wf_schedule* sch, const void* const* s_init, void* const* s_out,
@@ -995,6 +1131,7 @@ const char* wf_strerror(int32_t s) {
     case WF_EDEVICE: return "HIP runtime error";
     case WF_ENOMEM: return "device allocation failed";
     case WF_EUNSUPPORTED: return "map size or precision not supported";
+    case WF_ESCRATCH: return "workspace larger than the static scratch of wf_solve_noalloc";
     default: return "unknown status";
   }
 }

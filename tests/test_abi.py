@@ -57,7 +57,7 @@ def test_host_only_calls():
     lib.wf_schedule_default(ctypes.byref(s))
     assert s.kind == 1 and s.lambda0 == 1.0e4 and s.shrink_exp == 0.7
     assert list(s.beta) == [0.9, 0.9, 1.0] and s.chain == 0
-    for code in (0, 1, -1, -2, -3, -4, -5, -6):
+    for code in (0, 1, -1, -2, -3, -4, -5, -6, -7):
         assert wf.strerror(code)
     import paper_1704_00865_amd.nn as nn
     offs = nn.layer_offsets()
@@ -109,3 +109,32 @@ def test_host_side_argument_checks():
     assert lib.wf_solve_batch(None, 0, None, None, None, None, None, None) == -1
     assert lib.wf_nn_predict(None, 1, None, None, None, None, None) == -1
     assert lib.wf_nn_conv3x3(9, 1, 8, 8, 32, 32, None, None, None, None, None, None) == -1
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libwf.so not built")
+def test_noalloc_rejects_what_its_scratch_cannot_hold():
+    """wf_solve_noalloc checks shape, schedule and workspace size on the host
+    before any device call (the pointers below are never dereferenced)."""
+    import paper_1704_00865_amd as wf
+    lib = wf.load()
+    assert lib.wf_noalloc_scratch_bytes() == 32 << 20
+    fake = ctypes.c_void_p(0x1000)
+    inp = wf._Inputs(fake, fake, fake, None, None, None)
+    out = ctypes.c_void_p(0x2000)
+
+    def call(ny, nx, prec, **kw):
+        s = wf.Schedule(lambdas=[1.0], rtol=0.0, max_sweeps=kw.get("max_sweeps", 100),
+                        monitor_every=kw.get("monitor_every", 16))
+        c, keep = s._c()
+        shape = wf._Shape(ny, nx, prec)
+        return lib.wf_solve_noalloc(ctypes.byref(shape), ctypes.byref(inp), ctypes.byref(c),
+                                    None, out, None, None, None)
+    # only calls that are rejected before any device work: the pointers are
+    # fake
+    assert call(2048, 2048, 0) == -7          # 4 M pixels do not fit in 32 MiB
+    assert call(1024, 1024, 0) == -7
+    assert call(1024, 1024, 1) == -7
+    assert call(768, 768, 1) == -7
+    assert call(256, 256, 0, max_sweeps=70000) == -7
+    assert call(100, 256, 0) == -6
+    assert lib.wf_solve_noalloc(None, ctypes.byref(inp), None, None, out, None, None, None) == -1
