@@ -142,6 +142,7 @@ typedef struct {         /* HOST struct filled by wf_solve */
   double phi;            /* white floor moved to the stripe level                       */
   double kernel_ms[4];   /* profiling (wf_ctx_set_profiling): summed durations of the   */
   int32_t kernel_launches[4]; /* row, column, monitor and controller kernels timed     */
+  int32_t refine_rounds; /* wf_solve_refined: float32 solves run (0 for other calls)     */
 } wf_report;
 
 /* Create a context (device workspace, FFT tables) for one map shape on the
@@ -186,6 +187,37 @@ wf_status wf_solve_noalloc(const wf_shape* shape, const wf_inputs* in, const wf_
                            const void* s_init, void* s_out, wf_report* rep, double* trace,
                            hipStream_t stream);
 size_t wf_noalloc_scratch_bytes(void);
+
+/* Mixed-precision iterative refinement of the Wiener filter (the refinement
+ * is not from the paper; each round is the paper's iteration): float32
+ * sweeps, float64 residual.  Round 0 solves the data on the float32
+ * context with schedule `first`; x = S^-1 s of that solve is accumulated in
+ * float64 on the float64 context and its residual Delta d = d_rec - d of
+ * Section 2 is evaluated in float64; while rho > rtol and fewer than
+ * max_rounds corrections have run, -Delta d (observed pixels) is solved on
+ * the float32 context with schedule `corr` and its x is added.  The filter
+ * is linear with inverse (I + N S^-1) on the observed pixels, so each round
+ * divides rho by roughly the float32 solve's relative accuracy.  The
+ * masked part of x is not seen by the residual: rho_mask stays at the
+ * level of round 0 (the same holds for any solve stopped on rho alone).
+ *   ctx32, ctx64  contexts of the same shape on the current device, WF_F32
+ *                 and WF_F64;
+ *   in            float64 DEVICE inputs (as for ctx64); float32 copies are
+ *                 made on ctx32 (allocated on its first refined solve);
+ *   first, corr   schedules of round 0 and of the corrections (field_mode
+ *                 0; their rtol applies to each float32 solve, relative to
+ *                 its own right-hand side);
+ *   s_out         float64 DEVICE [ny*nx], s = S x;
+ *   rep           rho and rho_mask of the final float64 residual, total
+ *                 sweeps, refine_rounds (= n_records); status WF_OK when
+ *                 rho <= rtol, WF_NOT_CONVERGED otherwise (s_out valid);
+ *   trace         HOST [4 * (max_rounds + 1)] rows of (round, sweeps so far,
+ *                 rho, rho_mask) after each round, or NULL.
+ * Synchronises stream. */
+wf_status wf_solve_refined(void* ctx32, void* ctx64, const wf_inputs* in,
+                           const wf_schedule* first, const wf_schedule* corr, int32_t max_rounds,
+                           double rtol, void* s_out, wf_report* rep, double* trace,
+                           hipStream_t stream);
 
 /* Largest batch wf_solve_batch accepts. */
 #define WF_BATCH_MAX 1024

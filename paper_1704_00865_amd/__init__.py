@@ -18,7 +18,7 @@ import numpy as np
 
 __all__ = [
     "load", "Context", "Schedule", "solve", "rfft2", "irfft2", "strerror",
-    "WFError", "STATUS", "CHAINS", "solve_batch", "solve_noalloc",
+    "WFError", "STATUS", "CHAINS", "solve_batch", "solve_noalloc", "solve_refined",
 ]
 
 _LIB_PATH = os.environ.get("WF_LIBRARY") or os.path.join(
@@ -67,13 +67,13 @@ class _Report(ctypes.Structure):
                 ("d2", ctypes.c_double), ("chi2_joint", ctypes.c_double),
                 ("masked_x_norm", ctypes.c_double), ("tau", ctypes.c_double * 3),
                 ("phi", ctypes.c_double), ("kernel_ms", ctypes.c_double * 4),
-                ("kernel_launches", ctypes.c_int32 * 4)]
+                ("kernel_launches", ctypes.c_int32 * 4), ("refine_rounds", ctypes.c_int32)]
 
 
 EXPORTS = ("wf_ctx_create", "wf_ctx_destroy", "wf_schedule_default", "wf_solve", "wf_rfft2",
            "wf_irfft2", "wf_ctx_set_profiling", "wf_supported", "wf_strerror", "wf_tile_count",
            "wf_ctx_set_tile", "wf_ctx_get_tile", "wf_inverse_noise_weight", "wf_solve_batch",
-           "wf_solve_noalloc", "wf_noalloc_scratch_bytes")
+           "wf_solve_noalloc", "wf_noalloc_scratch_bytes", "wf_solve_refined")
 
 
 def load():
@@ -111,6 +111,10 @@ def load():
     lib.wf_solve_noalloc.restype = i32
     lib.wf_noalloc_scratch_bytes.argtypes = []
     lib.wf_noalloc_scratch_bytes.restype = ctypes.c_size_t
+    lib.wf_solve_refined.argtypes = [vp, vp, ctypes.POINTER(_Inputs), ctypes.POINTER(_Schedule),
+                                     ctypes.POINTER(_Schedule), i32, ctypes.c_double, vp,
+                                     ctypes.POINTER(_Report), ctypes.POINTER(ctypes.c_double), vp]
+    lib.wf_solve_refined.restype = i32
     lib.wf_rfft2.argtypes = [vp, vp, vp, vp]
     lib.wf_rfft2.restype = i32
     lib.wf_irfft2.argtypes = [vp, vp, vp, vp]
@@ -197,7 +201,8 @@ def _report(rep) -> dict:
                 n_levels=rep.n_levels, lam=rep.lam, rho=rep.rho, rho_mask=rep.rho_mask,
                 dd2=rep.dd2, d2=rep.d2, chi2_joint=rep.chi2_joint,
                 masked_x_norm=rep.masked_x_norm, tau=list(rep.tau), phi=rep.phi,
-                kernel_ms=list(rep.kernel_ms), kernel_launches=list(rep.kernel_launches))
+                kernel_ms=list(rep.kernel_ms), kernel_launches=list(rep.kernel_launches),
+                refine_rounds=rep.refine_rounds)
 
 
 def _stream_ptr(torch, device):
@@ -361,6 +366,45 @@ def solve(d, s_k, n_pix, p_oof=None, p_stripe=None, mask=None, *, schedule=Sched
         return ctx.solve(d, s_k, n_pix, p_oof, p_stripe, mask, schedule=schedule, s_init=s_init)
     finally:
         ctx.close()
+
+
+def solve_refined(ctx32, ctx64, d, s_k, n_pix, p_oof=None, p_stripe=None, mask=None, *,
+                  first: Schedule, corr: Schedule, max_rounds: int = 4, rtol: float = 1e-6,
+                  out=None):
+    """``wf_solve_refined``: float32 solves on ``ctx32`` refined with float64
+    residuals on ``ctx64`` (same shape).  Inputs are float64 tensors as for
+    ``ctx64``.  Returns (s float64, report dict, trace array of (round,
+    sweeps so far, rho, rho_mask) after each round)."""
+    import torch
+    lib = load()
+    if ctx32.dtype != torch.float32 or ctx64.dtype != torch.float64:
+        raise ValueError("ctx32 must be float32 and ctx64 float64")
+    ny, nx = ctx64.ny, ctx64.nx
+    nh = nx // 2 + 1
+    ctx64._check(d, (ny, nx), "d")
+    ctx64._check(s_k, (ny, nh), "s_k")
+    ctx64._check(n_pix, (ny, nx), "n_pix")
+    ctx64._check(p_oof, (ny, nh), "p_oof")
+    ctx64._check(p_stripe, (ny,), "p_stripe")
+    ctx64._check(mask, (ny, nx), "mask", torch.uint8)
+    if out is None:
+        out = torch.empty((ny, nx), dtype=torch.float64, device=ctx64.device)
+    ctx64._check(out, (ny, nx), "out")
+    inp = _inputs(d, s_k, n_pix, p_oof, p_stripe, mask)
+    s1, k1 = first._c()
+    s2, k2 = corr._c()
+    rep = _Report()
+    trace = np.zeros((int(max_rounds) + 1, 4), dtype=np.float64)
+    with torch.cuda.device(ctx64.device):
+        st = lib.wf_solve_refined(ctx32._h, ctx64._h, ctypes.byref(inp), ctypes.byref(s1),
+                                  ctypes.byref(s2), int(max_rounds), ctypes.c_double(rtol),
+                                  out.data_ptr(), ctypes.byref(rep),
+                                  trace.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                  _stream_ptr(torch, ctx64.device))
+    del k1, k2
+    if st < 0:
+        raise WFError(st, "wf_solve_refined")
+    return out, _report(rep), trace[: rep.refine_rounds]
 
 
 def solve_noalloc(d, s_k, n_pix, p_oof=None, p_stripe=None, mask=None, *,

@@ -779,6 +779,7 @@ __global__ __launch_bounds__(TC * (NY / col_elems<T, NY>()), (col_min_waves<T, N
     return;
   }
 
+
   if constexpr (SW) {
     ChainCoef<T> k;
     k.TW = (T)(lam * a.tauW);
@@ -981,7 +982,7 @@ __global__ __launch_bounds__(kTCM * (NY / mon_elems<NY>())) void mon_col_kernel(
     if (valid) {
       cx<T> v = ldc(tf + idx);
       if (mir) v.im = -v.im;
-      const double inv = 1.0 / ((double)msc[idx] + Tf);
+      const double inv = m.x_direct ? 1.0 : 1.0 / ((double)msc[idx] + Tf);
       const double xr = (double)v.re * inv, xi = (double)v.im * inv;
       const double f = (mode == MON_OUTPUT) ? (m.out_chain ? (double)msc[idx] : (double)msig[idx])
                                             : (double)msy[idx];
@@ -1082,8 +1083,10 @@ __global__ __launch_bounds__(kTRM * (NX / mon_elems<NX>())) void mon_row_kernel(
     } else if (mn2[i] >= (T)0) {
       const double dd = yv + (double)mnp[i] * xv - (double)md[i];
       a_dd += dd * dd;
+      if (mode == MON_REFINE) gmem(m.rout)[i] = (float)(-dd);
     } else {
       a_mx += xv * xv;
+      if (mode == MON_REFINE) gmem(m.rout)[i] = 0.0f;
     }
   }
   if (mode == MON_OUTPUT) return;
@@ -1095,6 +1098,47 @@ __global__ __launch_bounds__(kTRM * (NX / mon_elems<NX>())) void mon_row_kernel(
     part[2 * band + 1] = a_mx;
   }
 }
+
+// Refinement: x = S_chain^-1 u of a finished solve, t / (S_chain + T) per mode
+// in float64 from the solve's stored messenger t (state layout [kx][ky]; the
+// real columns k_x = 0 and nx/2 hold k_y <= ny/2 only, the rest is the
+// conjugate of the mirrored mode), added to (or, first, stored in) xacc.
+template <class S>
+__global__ __launch_bounds__(256) void accum_x_kernel(const cx<S>* __restrict__ tA,
+                                                      const S* __restrict__ sc, double Tf,
+                                                      int ny, int nx, int first,
+                                                      cx<double>* __restrict__ xacc) {
+  const int nh = nx / 2 + 1;
+  const int64_t n = (int64_t)nh * ny;
+  for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < n;
+       j += (int64_t)gridDim.x * blockDim.x) {
+    const int kx = (int)(j / ny), ky = (int)(j - (int64_t)kx * ny);
+    const bool mir = (kx == 0 || kx == nx / 2) && ky > ny / 2;
+    const int64_t src = mir ? (int64_t)kx * ny + (ny - ky) : j;
+    const cx<S> t = tA[src];
+    const double inv = 1.0 / ((double)sc[src] + Tf);
+    const double xr = (double)t.re * inv, xi = (mir ? -(double)t.im : (double)t.im) * inv;
+    if (first) {
+      xacc[j] = cx<double>{xr, xi};
+    } else {
+      const cx<double> o = xacc[j];
+      xacc[j] = cx<double>{o.re + xr, o.im + xi};
+    }
+  }
+}
+
+// precision conversion of an input array (refinement: float32 copies)
+template <class S, class D>
+__global__ __launch_bounds__(256) void convert_kernel(const S* __restrict__ src, int64_t n,
+                                                      D* __restrict__ dst) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    dst[i] = (D)src[i];
+}
+
+// fixed-order sum of the monitor's (dd^2, masked x^2) block pairs
+__global__ __launch_bounds__(256) void pair_sum_kernel(const double* __restrict__ part, int nblk,
+                                                       double* __restrict__ out);
 
 // fill / scale helpers for the inverse-noise weighting (S = alpha I)
 template <class T>
@@ -1112,6 +1156,22 @@ __global__ __launch_bounds__(256) void scale_kernel(T* __restrict__ x, int64_t n
 }
 
 #if WF_PART & 1
+__global__ __launch_bounds__(256) void pair_sum_kernel(const double* __restrict__ part, int nblk,
+                                                       double* __restrict__ out) {
+  __shared__ double sh[16];
+  double a = 0.0, b = 0.0;
+  for (int i = threadIdx.x; i < nblk; i += blockDim.x) {
+    a += part[2 * i];
+    b += part[2 * i + 1];
+  }
+  a = block_reduce<RED_SUM>(a, sh);
+  b = block_reduce<RED_SUM>(b, sh);
+  if (threadIdx.x == 0) {
+    out[0] = a;
+    out[1] = b;
+  }
+}
+
 // One block: fixed-order reduction of the monitor partials, then the cooling
 // schedule (fixed array, or the plateau rule of Section 3.3) and the stop test.
 __global__ __launch_bounds__(256) void controller_kernel(const CtrlArgs* __restrict__ argv) {

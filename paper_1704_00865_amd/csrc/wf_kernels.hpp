@@ -25,7 +25,9 @@ enum FourierKind : int32_t {
 enum RowMode : int32_t { ROW_SWEEP = 0, ROW_R2C = 1, ROW_C2R = 2, ROW_SWEEP_J = 3 };
 enum ColMode : int32_t { COL_SWEEP = 0, COL_FWD_OUT = 1, COL_INV_IN = 2, COL_INIT = 3,
                          COL_SWEEP_J = 4 };
-enum MonMode : int32_t { MON_RESIDUAL = 0, MON_OUTPUT = 1 };
+// MON_REFINE: the residual sums of MON_RESIDUAL and the float32 right-hand
+// side d - d_rec (zero on masked pixels) to rout.
+enum MonMode : int32_t { MON_RESIDUAL = 0, MON_OUTPUT = 1, MON_REFINE = 3 };
 
 // Schedule state resident on the device.  Sweep kernels read it; only the
 // controller kernel (after each monitor) writes it.
@@ -115,6 +117,8 @@ struct MonArgs {
   double tau_first;
   double scale;
   int32_t out_chain;    // output u = S_chain x instead of s = S x
+  int32_t x_direct;     // tfirst holds x itself (refinement), not a messenger
+  float* rout;          // MON_REFINE: [ny][nx] right-hand side of the next solve
 };
 
 // per-map arguments of the controller (one block per map)

@@ -35,6 +35,12 @@ template <class T>
 hipError_t launch_mon_row(const MonArgs<T>& m, const MonArgs<T>* argv, int nmaps, int mode,
                           hipStream_t st);
 hipError_t launch_controller(const CtrlArgs* argv, int nmaps, hipStream_t st);
+// refinement helpers: x of a float32 solve added to a float64 accumulator,
+// float64 -> float32 input copies, and the monitor's pair sums
+hipError_t launch_accum_x(const void* tA, const float* sc, double Tf, int ny, int nx, int first,
+                          void* xacc, hipStream_t st);
+hipError_t launch_to_float(const double* src, int64_t n, float* dst, hipStream_t st);
+hipError_t launch_pair_sum(const double* part, int nblk, double* out, hipStream_t st);
 template <class T>
 hipError_t launch_stats(const T* d, const T* npix, const uint8_t* mask, const T* sk, const T* poof,
                         const T* pst, int ny, int nx, double* part, int nblk, double* out_pix,

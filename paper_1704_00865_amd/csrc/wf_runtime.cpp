@@ -73,6 +73,17 @@ struct Ctx {
   // workspace carved from the library's static scratch (wf_solve_noalloc):
   // no events, no pinned memory, nothing to free
   bool no_alloc = false;
+  // iterative refinement (wf_solve_refined), allocated on first use: on the
+  // float32 context the float32 copies of the inputs (the data copy then
+  // holds each round's right-hand side) and a dummy output; on the float64
+  // context the monitor argument blocks of its three passes
+  void* ref_d = nullptr;
+  void* ref_npix = nullptr;
+  void* ref_sk = nullptr;
+  void* ref_poof = nullptr;
+  void* ref_pst = nullptr;
+  void* ref_out = nullptr;
+  void* ref_margs = nullptr;
 };
 
 // Every device buffer of a context with its size: take(&pointer, bytes) is
@@ -143,7 +154,8 @@ void make_table(std::vector<T>& out, int n) {
 void free_ctx(Ctx* c) {
   void* bufs[] = {c->B, c->tA, c->dA, c->tB, c->sc, c->nbA, c->sy, c->sig, c->nbar2, c->twx, c->twy,
                   c->Mx, c->My, c->part, c->jpart, c->stats, c->sch, c->lam, c->trace,
-                  c->alpha_sk, c->d_args, c->d_margs, c->d_ctrl};
+                  c->alpha_sk, c->d_args, c->d_margs, c->d_ctrl, c->ref_d, c->ref_npix,
+                  c->ref_sk, c->ref_poof, c->ref_pst, c->ref_out, c->ref_margs};
   for (void* p : bufs)
     if (p) (void)hipFree(p);
   if (c->h_ring) (void)hipHostFree(c->h_ring);
@@ -585,11 +597,13 @@ void fill_report(wf_report* rep, const DevSched& fin, const Chain& ch, const dou
 
 template <class T>
 wf_status solve_t(Ctx* c, const wf_inputs* in, const wf_schedule* s, const void* s_init,
-                  void* s_out, wf_report* rep, double* trace, hipStream_t st) {
+                  void* s_out, wf_report* rep, double* trace, hipStream_t st,
+                  Chain* chain_out = nullptr) {
   std::vector<MapRun<T>> runs(1);
   MapRun<T>& r = runs[0];
   wf_status ss = map_setup<T>(c, in, s, s_init, s_out, c->sch, r, st);
   if (ss != WF_OK) return ss;
+  if (chain_out) *chain_out = r.ch;
   // argument blocks for the single-map launches
   std::memcpy(c->h_args, &r.a, sizeof(r.a));
   std::memcpy(c->h_margs, &r.m, sizeof(r.m));
@@ -843,6 +857,123 @@ wf_status solve_batch_t(Ctx** ctxs, int n, const wf_inputs* ins, const wf_schedu
   return ret;
 }
 
+// ----- iterative refinement: float32 solves, float64 residual ---------------
+//
+// x = S^-1 s is accumulated in float64 (state layout [kx][ky], unnormalised
+// like every Fourier field here) on the float64 context:
+//   round 0: solve the data with float32 sweeps; x_acc = x of that solve;
+//   then, while rho > rtol: evaluate Delta d = d_rec(x_acc) - d in float64
+//   and solve -Delta d (observed pixels; 0 on masked ones) with float32
+//   sweeps; x_acc += x of that solve.
+// The filter is linear and (I + N S^-1) is its inverse on the observed
+// pixels (Section 2), so each correction removes the residual of x_acc up
+// to the float32 solve's own relative accuracy.  Output s = S x_acc.
+wf_status ensure(void** p, size_t bytes) {
+  return *p ? WF_OK : alloc(p, bytes);
+}
+
+wf_status solve_refined(Ctx* c32, Ctx* c64, const wf_inputs* in, const wf_schedule* first,
+                        const wf_schedule* corr, int max_rounds, double rtol, void* s_out,
+                        wf_report* rep, double* trace, hipStream_t st) {
+  const size_t ny = c32->ny, nx = c32->nx, nh = c32->nh;
+  const size_t npix = ny * nx, modes = ny * nh;
+  wf_status e;
+  if ((e = ensure(&c32->ref_d, npix * 4)) != WF_OK) return e;
+  if ((e = ensure(&c32->ref_npix, npix * 4)) != WF_OK) return e;
+  if ((e = ensure(&c32->ref_sk, modes * 4)) != WF_OK) return e;
+  if ((e = ensure(&c32->ref_out, npix * 4)) != WF_OK) return e;
+  if (in->p_oof && (e = ensure(&c32->ref_poof, modes * 4)) != WF_OK) return e;
+  if (in->p_stripe && (e = ensure(&c32->ref_pst, ny * 4)) != WF_OK) return e;
+  if ((e = ensure(&c64->ref_margs, 2 * sizeof(MonArgs<double>))) != WF_OK) return e;
+  // float64 side: validation and the per-mode arrays (S + N_F, S, mask sign)
+  std::vector<MapRun<double>> runs(1);
+  MapRun<double>& r64 = runs[0];
+  wf_status ss = map_setup<double>(c64, in, first, nullptr, s_out, c64->sch, r64, st);
+  if (ss != WF_OK) return ss;
+  // float32 copies of the inputs
+  WF_TRY(launch_to_float((const double*)in->d, (int64_t)npix, (float*)c32->ref_d, st));
+  WF_TRY(launch_to_float((const double*)in->n_pix, (int64_t)npix, (float*)c32->ref_npix, st));
+  WF_TRY(launch_to_float((const double*)in->s_k, (int64_t)modes, (float*)c32->ref_sk, st));
+  if (in->p_oof)
+    WF_TRY(launch_to_float((const double*)in->p_oof, (int64_t)modes, (float*)c32->ref_poof, st));
+  if (in->p_stripe)
+    WF_TRY(launch_to_float((const double*)in->p_stripe, (int64_t)ny, (float*)c32->ref_pst, st));
+  wf_inputs in32 = *in;
+  in32.d = c32->ref_d;
+  in32.n_pix = c32->ref_npix;
+  in32.s_k = c32->ref_sk;
+  in32.p_oof = in->p_oof ? c32->ref_poof : nullptr;
+  in32.p_stripe = in->p_stripe ? c32->ref_pst : nullptr;
+  // monitor passes on the float64 context, x read directly from x_acc:
+  // [0] residual and the next right-hand side, [1] output s = S x
+  void* xacc = c64->dA;
+  MonArgs<double> mh[2];
+  for (int i = 0; i < 2; ++i) {
+    mh[i] = mon_args<double>(c64, in, r64.ch);
+    mh[i].tfirst = xacc;
+    mh[i].x_direct = 1;
+    mh[i].out_chain = 0;
+    mh[i].rout = (float*)c32->ref_d;
+  }
+  mh[1].s_out = s_out;
+  const MonArgs<double>* dm = (const MonArgs<double>*)c64->ref_margs;
+  WF_TRY(hipMemcpyAsync(c64->ref_margs, mh, sizeof(mh), hipMemcpyHostToDevice, st));
+  WF_TRY(hipStreamSynchronize(st));  // mh is this frame's memory
+  const double d2 = r64.pix[3], nu = r64.pix[2];
+  int sweeps = 0, rounds = 0, last_status = WF_OK;
+  double rho = INFINITY, rho_mask = INFINITY, dd2 = 0.0;
+  for (int j = 0; j <= max_rounds; ++j) {
+    wf_report rj;
+    Chain chj;
+    const wf_status sj = solve_t<float>(c32, &in32, j == 0 ? first : corr, nullptr, c32->ref_out,
+                                        &rj, nullptr, st, &chj);
+    if (sj < 0) return sj;
+    last_status = sj;
+    sweeps += rj.sweeps;
+    rounds = j + 1;
+    WF_TRY(launch_accum_x(c32->tA, (const float*)c32->sc, rj.lambda * chj.tau_first, (int)ny,
+                          (int)nx, j == 0, xacc, st));
+    // float64 residual of x_acc; its negative is the next right-hand side
+    WF_TRY(launch_mon_col<double>(mh[0], dm, 1, MON_REFINE, st));
+    WF_TRY(launch_mon_row<double>(mh[0], dm, 1, MON_REFINE, st));
+    WF_TRY(launch_pair_sum(c64->part, (int)(ny / kTRM), c64->stats, st));
+    WF_TRY(hipMemcpyAsync(c64->h_stats, c64->stats, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
+    WF_TRY(hipStreamSynchronize(st));
+    dd2 = c64->h_stats[0];
+    rho = std::sqrt(dd2 / d2);
+    rho_mask = nu * std::sqrt(c64->h_stats[1]) / std::sqrt(d2);
+    if (!std::isfinite(dd2)) return WF_ENONFINITE;
+    if (trace) {
+      double* tr = trace + 4 * j;
+      tr[0] = j;
+      tr[1] = sweeps;
+      tr[2] = rho;
+      tr[3] = rho_mask;
+    }
+    if (rho <= rtol) break;
+  }
+  WF_TRY(launch_mon_col<double>(mh[1], dm + 1, 1, MON_OUTPUT, st));
+  WF_TRY(launch_mon_row<double>(mh[1], dm + 1, 1, MON_OUTPUT, st));
+  WF_TRY(hipStreamSynchronize(st));
+  const int status = rho <= rtol ? WF_OK : WF_NOT_CONVERGED;
+  if (rep) {
+    std::memset(rep, 0, sizeof(*rep));
+    rep->status = status;
+    rep->sweeps = sweeps;
+    rep->n_levels = r64.ch.n_levels;
+    rep->lambda = 1.0;
+    rep->rho = rho;
+    rep->rho_mask = rho_mask;
+    rep->dd2 = dd2;
+    rep->d2 = d2;
+    rep->masked_x_norm = std::sqrt(c64->h_stats[1]);
+    rep->refine_rounds = rounds;
+    rep->n_records = rounds;
+    (void)last_status;
+  }
+  return (wf_status)status;
+}
+
 // ----- the entry point that allocates nothing ------------------------------
 //
 // wf_solve_noalloc carves a context's workspace out of this array instead of
@@ -1025,6 +1156,26 @@ wf_status wf_solve_noalloc(const wf_shape* shape, const wf_inputs* in, const wf_
 }
 
 size_t wf_noalloc_scratch_bytes(void) { return kStaticBytes; }
+
+wf_status wf_solve_refined(void* ctx32, void* ctx64, const wf_inputs* in,
+                           const wf_schedule* first, const wf_schedule* corr, int32_t max_rounds,
+                           double rtol, void* s_out, wf_report* rep, double* trace,
+                           hipStream_t stream) {
+  Ctx* c32 = (Ctx*)ctx32;
+  Ctx* c64 = (Ctx*)ctx64;
+  if (!c32 || !c64 || !in || !first || !corr || !s_out || !in->d || !in->s_k || !in->n_pix)
+    return WF_EINVAL;
+  if (c32->prec != WF_F32 || c64->prec != WF_F64) return WF_EINVAL;
+  if (c32->ny != c64->ny || c32->nx != c64->nx || c32->device != c64->device) return WF_EINVAL;
+  if (max_rounds < 0 || !(rtol >= 0)) return WF_EINVAL;
+  wf_status v = check_schedule(first);
+  if (v == WF_OK) v = check_schedule(corr);
+  if (v != WF_OK) return v;
+  if (first->field_mode != 0 || corr->field_mode != 0) return WF_EINVAL;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev != c32->device) return WF_EINVAL;
+  return solve_refined(c32, c64, in, first, corr, max_rounds, rtol, s_out, rep, trace, stream);
+}
 
 wf_status wf_solve_batch(void* const* ctxs, int32_t n, const wf_inputs* inputs,
                          const wf_schedule* sch, const void* const* s_init, void* const* s_out,
