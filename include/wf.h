@@ -209,7 +209,8 @@ size_t wf_noalloc_scratch_bytes(void);
  *                 its own right-hand side);
  *   s_out         float64 DEVICE [ny*nx], s = S x;
  *   rep           rho and rho_mask of the final float64 residual, total
- *                 sweeps, refine_rounds (= n_records); status WF_OK when
+ *                 sweeps, refine_rounds (= n_records), the float32 solves'
+ *                 kernel timing when ctx32 profiles; status WF_OK when
  *                 rho <= rtol, WF_NOT_CONVERGED otherwise (s_out valid);
  *   trace         HOST [4 * (max_rounds + 1)] rows of (round, sweeps so far,
  *                 rho, rho_mask) after each round, or NULL.

@@ -921,6 +921,8 @@ wf_status solve_refined(Ctx* c32, Ctx* c64, const wf_inputs* in, const wf_schedu
   WF_TRY(hipStreamSynchronize(st));  // mh is this frame's memory
   const double d2 = r64.pix[3], nu = r64.pix[2];
   int sweeps = 0, rounds = 0, last_status = WF_OK;
+  double prof_ms[4] = {0, 0, 0, 0};  // per-kernel timing of the float32 solves
+  int prof_n[4] = {0, 0, 0, 0};
   double rho = INFINITY, rho_mask = INFINITY, dd2 = 0.0;
   for (int j = 0; j <= max_rounds; ++j) {
     wf_report rj;
@@ -930,6 +932,10 @@ wf_status solve_refined(Ctx* c32, Ctx* c64, const wf_inputs* in, const wf_schedu
     if (sj < 0) return sj;
     last_status = sj;
     sweeps += rj.sweeps;
+    for (int i = 0; i < 4; ++i) {
+      prof_ms[i] += rj.kernel_ms[i];
+      prof_n[i] += rj.kernel_launches[i];
+    }
     rounds = j + 1;
     WF_TRY(launch_accum_x(c32->tA, (const float*)c32->sc, rj.lambda * chj.tau_first, (int)ny,
                           (int)nx, j == 0, xacc, st));
@@ -969,6 +975,10 @@ wf_status solve_refined(Ctx* c32, Ctx* c64, const wf_inputs* in, const wf_schedu
     rep->masked_x_norm = std::sqrt(c64->h_stats[1]);
     rep->refine_rounds = rounds;
     rep->n_records = rounds;
+    for (int i = 0; i < 4; ++i) {
+      rep->kernel_ms[i] = prof_ms[i];
+      rep->kernel_launches[i] = prof_n[i];
+    }
     (void)last_status;
   }
   return (wf_status)status;
