@@ -244,26 +244,55 @@ struct twp_offsets {
   static constexpr int size = N - p1;
 };
 
-// Fill the pass-major table twp (LDS, twp_offsets::size entries) from the
-// natural table tw; threads tid of nthr share the work.
-template <class T, int N, int E, class TW>
-__device__ __forceinline__ void stage_twiddles(cx<T>* twp, TW tw, int tid, int nthr) {
+// Natural-table index of entry e of the pass-major table of plan_for<N, E>.
+template <int N, int E>
+__device__ __forceinline__ int twp_source(int e) {
   using PL = plan_for<N, E>;
   using O = twp_offsets<N, E>;
-  for (int e = tid; e < O::size; e += nthr) {
-    int j;
-    if (e < O::o3) {
-      const int o = e - O::o2, m = 1 + o / O::p1, k = o - (m - 1) * O::p1;
-      j = m * k * (N / (O::p1 * PL::r1));
-    } else if (e < O::o4) {
-      const int o = e - O::o3, m = 1 + o / O::p2, k = o - (m - 1) * O::p2;
-      j = m * k * (N / (O::p2 * PL::r2));
-    } else {
-      const int o = e - O::o4, m = 1 + o / O::p3, k = o - (m - 1) * O::p3;
-      j = m * k * (N / (O::p3 * PL::r3));
-    }
-    twp[e] = ldc(tw + j);
+  if (e < O::o3) {
+    const int o = e - O::o2, m = 1 + o / O::p1, k = o - (m - 1) * O::p1;
+    return m * k * (N / (O::p1 * PL::r1));
+  } else if (e < O::o4) {
+    const int o = e - O::o3, m = 1 + o / O::p2, k = o - (m - 1) * O::p2;
+    return m * k * (N / (O::p2 * PL::r2));
   }
+  const int o = e - O::o4, m = 1 + o / O::p3, k = o - (m - 1) * O::p3;
+  return m * k * (N / (O::p3 * PL::r3));
+}
+
+// Staging of the pass-major table into LDS by NTHR threads, in two steps so
+// that a kernel can issue every global load it needs (its own data and the
+// table) before the first wait: load() fetches this thread's share into
+// registers, store() writes it to the LDS table.
+template <class T, int N, int E, int NTHR>
+struct TwiddleStage {
+  using O = twp_offsets<N, E>;
+  static constexpr int PER = (O::size + NTHR - 1) / NTHR;
+  cx<T> v[PER];
+  template <class TW>
+  __device__ __forceinline__ void load(TW tw, int tid) {
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+      const int e = tid + i * NTHR;
+      if (e < O::size) v[i] = ldc(tw + twp_source<N, E>(e));
+    }
+  }
+  __device__ __forceinline__ void store(cx<T>* twp, int tid) const {
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+      const int e = tid + i * NTHR;
+      if (e < O::size) twp[e] = v[i];
+    }
+  }
+};
+
+// Fill the pass-major table twp (LDS, twp_offsets::size entries) from the
+// natural table tw with NTHR threads (loads first, then the LDS writes).
+template <class T, int N, int E, int NTHR, class TW>
+__device__ __forceinline__ void stage_twiddles(cx<T>* twp, TW tw, int tid) {
+  TwiddleStage<T, N, E, NTHR> s;
+  s.load(tw, tid);
+  s.store(twp, tid);
 }
 
 // One Stockham pass.  reg: the thread's E values; lds: this transform's

@@ -413,17 +413,31 @@ __global__ __launch_bounds__((RW / 2) * (NX / row_elems<T, NX>()), (min_waves<T,
   const WF_GLOBAL cx<T>* twg = gmem((const cx<T>*)a.twx);
   const int p = tid / NT, t = tid - p * NT;
   const int ya = y0 + 2 * p;
+  constexpr int NTHR = RP * NT;  // threads of the block
   cx<T> reg[E];
-  if constexpr (LTW) {
-    stage_twiddles<T, NX, E>(twl, twg, tid, blockDim.x);
-  }
 
   if constexpr (SW || MODE == ROW_C2R) {
-    for (int e = tid * EPC; e < SUB; e += blockDim.x * EPC) {
+    // every load of the band and of the twiddle table is issued before the
+    // first LDS write, so their latencies overlap
+    constexpr int NIT = SUB / (NTHR * EPC);
+    static_assert(NIT * NTHR * EPC == SUB, "the band splits evenly over the threads");
+    cx<T> bv[NIT][EPC];
+#pragma unroll
+    for (int it = 0; it < NIT; ++it) {
+      const int e = (tid + it * NTHR) * EPC;
+      const int g = e / (RW * TC), w = e - g * (RW * TC);
+      copy16(bv[it], &gband[g * (TR * TC) + w]);
+    }
+    TwiddleStage<T, NX, E, NTHR> tws;
+    if constexpr (LTW) tws.load(twg, tid);
+#pragma unroll
+    for (int it = 0; it < NIT; ++it) {
+      const int e = (tid + it * NTHR) * EPC;
       const int g = e / (RW * TC), w = e - g * (RW * TC);
       const int rr = w / TC, cc = w - rr * TC;
-      copy16(&lds[rr * RS + g * TC + cc], &gband[g * (TR * TC) + w]);
+      copy16(&lds[rr * RS + g * TC + cc], bv[it]);
     }
+    if constexpr (LTW) tws.store(twl, tid);
     __syncthreads();
     // Z = A + i B for the row pair; A, B Hermitian in k_x; slot 0 packs
     // (re of k_x = 0, re of k_x = nx/2)
@@ -493,6 +507,7 @@ __global__ __launch_bounds__((RW / 2) * (NX / row_elems<T, NX>()), (min_waves<T,
       }
     }
   } else {  // ROW_R2C
+    if constexpr (LTW) stage_twiddles<T, NX, E, NTHR>(twl, twg, tid);
 #pragma unroll
     for (int q = 0; q < E; ++q) {
       const size_t i0 = (size_t)ya * NX + t + NT * q;
@@ -663,9 +678,7 @@ __global__ __launch_bounds__(TC * (NY / col_elems<T, NY>()), (col_min_waves<T, N
   WF_GLOBAL cx<T>* gdA = gmem((cx<T>*)a.dA);
   WF_GLOBAL cx<T>* gtB = gmem((cx<T>*)a.tB);
   cx<T> reg[E];
-  if constexpr (LTW) {
-    stage_twiddles<T, NY, E>(twl, twg, tid, blockDim.x);
-  }
+  constexpr int NTHR = TC * NT;  // threads of the block
 
   // per-mode state and coefficients of this column, loaded in batches of 8
   // modes, or 4 where the registers are scarce (float64, 24 values per
@@ -694,6 +707,7 @@ __global__ __launch_bounds__(TC * (NY / col_elems<T, NY>()), (col_min_waves<T, N
   };
 
   if constexpr (MODE == COL_INV_IN) {
+    if constexpr (LTW) stage_twiddles<T, NY, E, NTHR>(twl, twg, tid);
 #pragma unroll
     for (int q = 0; q < E; ++q) {
       const int ky = t + NT * q;
@@ -710,9 +724,9 @@ __global__ __launch_bounds__(TC * (NY / col_elems<T, NY>()), (col_min_waves<T, N
     }
     if constexpr (LTW) __syncthreads();
   } else {
-    // every 16-byte load of this block's columns is issued before the first
-    // LDS store (0.7 us faster at 2048^2 than load-store pairs)
-    constexpr int NTHR = TC * NT;
+    // every 16-byte load of this block's columns, then the twiddle table's,
+    // is issued before the first LDS store (0.7 us faster at 2048^2 than
+    // load-store pairs)
     constexpr int NIT = E / EPC;
     static_assert(NIT * NTHR * EPC == TC * NY, "the columns split evenly over the threads");
     cx<T> bv[NIT][EPC];
@@ -722,6 +736,8 @@ __global__ __launch_bounds__(TC * (NY / col_elems<T, NY>()), (col_min_waves<T, N
       const int yb = e / TRTC, w = e - yb * TRTC;
       copy16(bv[it], &gB[((size_t)yb * G + g) * TRTC + w]);
     }
+    TwiddleStage<T, NY, E, NTHR> tws;
+    if constexpr (LTW) tws.load(twg, tid);
 #pragma unroll
     for (int it = 0; it < NIT; ++it) {
       const int e = (tid + it * NTHR) * EPC;
@@ -732,6 +748,7 @@ __global__ __launch_bounds__(TC * (NY / col_elems<T, NY>()), (col_min_waves<T, N
         lds[cc * YS + LM::at(yb * TR + r)] = bv[it][u];
       }
     }
+    if constexpr (LTW) tws.store(twl, tid);
     __syncthreads();
 #pragma unroll
     for (int q = 0; q < E; ++q) reg[q] = lds[c * YS + LM::at(t + NT * q)];
@@ -968,7 +985,8 @@ __global__ __launch_bounds__(kTCM * (NY / mon_elems<NY>())) void mon_col_kernel(
   const WF_GLOBAL T* msy = gmem(m.sy);
   const WF_GLOBAL T* msig = gmem(m.sig);
   const WF_GLOBAL cx<T>* twg = gmem((const cx<T>*)m.twy);
-  if constexpr (LTW) stage_twiddles<T, NY, E>(twl, twg, tid, blockDim.x);
+  TwiddleStage<T, NY, E, kTCM * NT> tws;
+  if constexpr (LTW) tws.load(twg, tid);
   // x = t / (S_c + lambda tau) and the Fourier-diagonal products are formed
   // in float64 and rounded once to the transform precision
   cx<T> rx[E], ry[E];
@@ -993,7 +1011,10 @@ __global__ __launch_bounds__(kTCM * (NY / mon_elems<NY>())) void mon_col_kernel(
       ry[q] = cx<T>{(T)0, (T)0};
     }
   }
-  if constexpr (LTW) __syncthreads();
+  if constexpr (LTW) {
+    tws.store(twl, tid);
+    __syncthreads();
+  }
 #pragma unroll
   for (int field = 0; field < 2; ++field) {
     cx<T>* reg = field == 0 ? rx : ry;
@@ -1038,14 +1059,33 @@ __global__ __launch_bounds__(kTRM * (NX / mon_elems<NX>())) void mon_row_kernel(
   const WF_GLOBAL cx<T>* gx = gmem((const cx<T>*)m.Mx) + (size_t)band * BANDm;
   const WF_GLOBAL cx<T>* gy = gmem((const cx<T>*)m.My) + (size_t)band * BANDm;
   const WF_GLOBAL cx<T>* twg = gmem((const cx<T>*)m.twx);
-  if constexpr (LTW) stage_twiddles<T, NX, E>(twl, twg, tid, blockDim.x);
-  for (int e = tid; e < BANDm; e += blockDim.x) {
-    // tile order [kx / kTCM][row][kx % kTCM]
-    const int g = e / (kTRM * kTCM), w = e - g * (kTRM * kTCM);
-    const int rr = w / kTCM, kx = g * kTCM + (w - rr * kTCM);
-    lds[rr * RSm + kx] = ldc(gx + e);
-    lds[(kTRM + rr) * RSm + kx] = ldc(gy + e);
+  // the two bands' loads and the twiddle table's, all issued before the
+  // first LDS write
+  constexpr int NTHR = kTRM * NT;
+  constexpr int NB = (BANDm + NTHR - 1) / NTHR;
+  cx<T> bx[NB], by[NB];
+#pragma unroll
+  for (int i = 0; i < NB; ++i) {
+    const int e = tid + i * NTHR;
+    if (e < BANDm) {
+      bx[i] = ldc(gx + e);
+      by[i] = ldc(gy + e);
+    }
   }
+  TwiddleStage<T, NX, E, NTHR> tws;
+  if constexpr (LTW) tws.load(twg, tid);
+#pragma unroll
+  for (int i = 0; i < NB; ++i) {
+    const int e = tid + i * NTHR;
+    if (e < BANDm) {
+      // tile order [kx / kTCM][row][kx % kTCM]
+      const int g = e / (kTRM * kTCM), w = e - g * (kTRM * kTCM);
+      const int rr = w / kTCM, kx = g * kTCM + (w - rr * kTCM);
+      lds[rr * RSm + kx] = bx[i];
+      lds[(kTRM + rr) * RSm + kx] = by[i];
+    }
+  }
+  if constexpr (LTW) tws.store(twl, tid);
   __syncthreads();
   const int r = tid / NT, t = tid - r * NT;
   cx<T> reg[E];

@@ -84,6 +84,13 @@ struct Ctx {
   void* ref_pst = nullptr;
   void* ref_out = nullptr;
   void* ref_margs = nullptr;
+  // one chunk of the single-map solve recorded as a HIP graph on cap_stream,
+  // replayed for every chunk; valid for the (K, last sweep of the budget
+  // within a chunk, tiling, chain kind) it was recorded with
+  hipStream_t cap_stream = nullptr;
+  hipGraph_t chunk_graph = nullptr;
+  hipGraphExec_t chunk_exec = nullptr;
+  int chunk_key[4] = {-1, -1, -1, -1};
 };
 
 // Every device buffer of a context with its size: take(&pointer, bytes) is
@@ -167,6 +174,9 @@ void free_ctx(Ctx* c) {
     if (e) (void)hipEventDestroy(e);
   for (auto& e : c->prof_ev)
     if (e) (void)hipEventDestroy(e);
+  if (c->chunk_exec) (void)hipGraphExecDestroy(c->chunk_exec);
+  if (c->chunk_graph) (void)hipGraphDestroy(c->chunk_graph);
+  if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
   delete c;
 }
 
@@ -595,6 +605,41 @@ void fill_report(wf_report* rep, const DevSched& fin, const Chain& ch, const dou
   rep->phi = ch.phi;
 }
 
+// The chunk graph of a context for this solve: recorded on the context's
+// capture stream the first time (or when the key changed), then reused.  The
+// launches read everything that changes between solves from the device
+// argument blocks and schedule, so one recording serves every solve with
+// the same key.
+template <class T>
+wf_status chunk_graph(Ctx* c, std::vector<ShapeClass<T>>& cls, const std::vector<MapRun<T>>& runs,
+                      int K, hipGraphExec_t* out) {
+  const int key[4] = {K, (runs[0].h.max_sweeps - 1) % K, c->tile, runs[0].a.fk};
+  if (c->chunk_exec && std::memcmp(key, c->chunk_key, sizeof(key)) == 0) {
+    *out = c->chunk_exec;
+    return WF_OK;
+  }
+  if (c->chunk_exec) (void)hipGraphExecDestroy(c->chunk_exec);
+  if (c->chunk_graph) (void)hipGraphDestroy(c->chunk_graph);
+  c->chunk_exec = nullptr;
+  c->chunk_graph = nullptr;
+  if (!c->cap_stream) WF_TRY(hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
+  WF_TRY(hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
+  const wf_status es = enqueue_chunk<T>(cls, runs, (const CtrlArgs*)c->d_ctrl, 1, K, nullptr,
+                                        c->cap_stream);
+  hipGraph_t g = nullptr;
+  const hipError_t ce = hipStreamEndCapture(c->cap_stream, &g);
+  if (es != WF_OK) {
+    if (g) (void)hipGraphDestroy(g);
+    return es;
+  }
+  WF_TRY(ce);
+  c->chunk_graph = g;
+  WF_TRY(hipGraphInstantiate(&c->chunk_exec, g, nullptr, nullptr, 0));
+  std::memcpy(c->chunk_key, key, sizeof(key));
+  *out = c->chunk_exec;
+  return WF_OK;
+}
+
 template <class T>
 wf_status solve_t(Ctx* c, const wf_inputs* in, const wf_schedule* s, const void* s_init,
                   void* s_out, wf_report* rep, double* trace, hipStream_t st,
@@ -630,10 +675,21 @@ wf_status solve_t(Ctx* c, const wf_inputs* in, const wf_schedule* s, const void*
   }
   const int prof_chunks = kProfSlots / 6;
   int launched = 0;
+  // without profiling (whose events are recorded by the dispatches of the
+  // first sweeps) every chunk is the replayed graph
+  hipGraphExec_t exec = nullptr;
+  if (!prof && !c->no_alloc) {
+    wf_status gs = chunk_graph<T>(c, cls, runs, K, &exec);
+    if (gs != WF_OK) return gs;
+  }
   for (int ci = 0; ci < r.n_chunks; ++ci) {
-    hipEvent_t* ev = (prof && ci < prof_chunks) ? &c->prof_ev[6 * ci] : nullptr;
-    wf_status es = enqueue_chunk<T>(cls, runs, (const CtrlArgs*)c->d_ctrl, 1, K, ev, st);
-    if (es != WF_OK) return es;
+    if (exec) {
+      WF_TRY(hipGraphLaunch(exec, st));
+    } else {
+      hipEvent_t* ev = (prof && ci < prof_chunks) ? &c->prof_ev[6 * ci] : nullptr;
+      wf_status es = enqueue_chunk<T>(cls, runs, (const CtrlArgs*)c->d_ctrl, 1, K, ev, st);
+      if (es != WF_OK) return es;
+    }
     launched = ci + 1;
     if (c->no_alloc) {
       // no events: every kStaticCheck chunks the host waits for the stream
