@@ -170,6 +170,18 @@ def bench_batch(wf, synth, torch, dev, a):
                 p_stripe=t(p.p_stripe)) for p in probs]
     ctxs = [wf.Context(p.d.shape[0], p.d.shape[1], "f32", device=dev) for p in probs]
     outs = [torch.empty(p.d.shape, dtype=torch.float32, device=dev) for p in probs]
+    # autotune one map of each size; its tiling serves the size class
+    tiles = {}
+    for c, pb in zip(ctxs, pbs):
+        key = (c.ny, c.nx)
+        if key not in tiles:
+            times = c.autotune(pb["d"], pb["s_k"], pb["n_pix"], pb["p_oof"], pb["p_stripe"])
+            tiles[key] = (c.tile, times)
+            print(f"[bench] batch {key[0]}x{key[1]}: tiling {c.tile} "
+                  f"({', '.join(f'{k}: {v:.2f}' for k, v in times.items())} ms)",
+                  file=sys.stderr, flush=True)
+        else:
+            c.set_tile(tiles[key][0])
     lams = cooling_lambdas(400, a.sweeps, 1.0e4)
     sched = wf.Schedule(lambdas=lams, rtol=0.0, max_sweeps=a.sweeps,
                         monitor_every=a.monitor_every)
@@ -207,6 +219,10 @@ def bench_batch(wf, synth, torch, dev, a):
             "one_at_a_time_seconds": round(dts, 4),
             "speedup_vs_one_at_a_time": round(dts / dtb, 3),
             "algorithmic_GBps": round(gbs, 1), "frac_of_hbm_peak": round(gbs / HBM_PEAK_GBS, 4),
+            "tilings": {f"{k[0]}x{k[1]}": {"chosen": v[0],
+                                           "ms_per_48_sweeps": {str(t): round(m, 3)
+                                                                for t, m in v[1].items()}}
+                        for k, v in tiles.items()},
             "note": "sweep kernels only in the algorithmic bytes (monitor every "
                     f"{a.monitor_every} sweeps is extra work inside the time)"}
 
@@ -432,22 +448,11 @@ def main():
         if not ctx.set_tile(a.tile):
             raise SystemExit(f"tiling {a.tile} is not built for {n}x{n}")
     else:
-        # autotune: time a short solve with every tiling built for this size
-        probe = wf.Schedule(lambdas=lams[:48], rtol=0.0, max_sweeps=48,
-                            monitor_every=a.monitor_every, chain=a.chain)
-        for tile in range(wf.load().wf_tile_count()):
-            if not ctx.set_tile(tile):
-                continue
-            ctx.solve(*args, schedule=probe, out=out)
-            torch.cuda.synchronize()
-            tt = time.perf_counter()
-            for _ in range(2):
-                ctx.solve(*args, schedule=probe, out=out)
-            torch.cuda.synchronize()
-            tile_times[tile] = (time.perf_counter() - tt) / 2
-            print(f"[bench] tiling {tile}: {1e3 * tile_times[tile]:.2f} ms / 48 sweeps",
-                  file=sys.stderr, flush=True)
-        ctx.set_tile(min(tile_times, key=tile_times.get))
+        # the library's autotuner: a 48-sweep solve of this map in every
+        # tiling built for its size, keeping the fastest
+        tile_times = ctx.autotune(*args, sweeps=48)
+        for tile, ms in tile_times.items():
+            print(f"[bench] tiling {tile}: {ms:.2f} ms / 48 sweeps", file=sys.stderr, flush=True)
     for i in range(a.warmup):
         ctx.solve(*args, schedule=sched, out=out)
         print(f"[bench] warmup {i + 1}/{a.warmup} done", file=sys.stderr, flush=True)

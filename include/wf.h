@@ -275,10 +275,26 @@ wf_status wf_ctx_set_profiling(void* ctx, int32_t enable);
 /* Transit-buffer tilings (rows x columns per tile, rows per row block) the
  * library holds, and the one a context uses.  Only tiling 0..count-1 exist;
  * wf_ctx_set_tile returns WF_EUNSUPPORTED for a tiling not built for the
- * context's size and precision.  An autotuner times the candidates. */
+ * context's size and precision.  wf_autotune times the candidates. */
 int32_t wf_tile_count(void);
 wf_status wf_ctx_set_tile(void* ctx, int32_t tile);
 int32_t wf_ctx_get_tile(void* ctx);
+
+/* Autotuner (not from the paper): times a short solve of the caller's map
+ * (a fixed cooling ramp of `sweeps` sweeps, 1 <= sweeps <= 4096, monitor
+ * every 16) in every tiling built for the context's size and precision, and
+ * leaves the context on the fastest.  Tilings other than the default are
+ * built for float32 maps whose sides are 256, 768, 1536 or 2048.
+ *   in       as for wf_solve (DEVICE inputs of the map to tune on);
+ *   scratch  DEVICE [ny*nx] buffer of the context's precision, overwritten
+ *            with the probe solves' output;
+ *   ms       HOST [wf_tile_count()] milliseconds per probe solve, -1 for a
+ *            tiling not built, or NULL;
+ *   best     HOST, receives the chosen tiling, or NULL.
+ * Synchronises stream; a solve error is returned (the context keeps its
+ * previous tiling then). */
+wf_status wf_autotune(void* ctx, const wf_inputs* in, int32_t sweeps, void* scratch, double* ms,
+                      int32_t* best, hipStream_t stream);
 
 /* Sizes the library was built for, and its precision support. */
 int32_t wf_supported(int32_t ny, int32_t nx, int32_t precision);

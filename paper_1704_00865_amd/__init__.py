@@ -73,7 +73,7 @@ class _Report(ctypes.Structure):
 EXPORTS = ("wf_ctx_create", "wf_ctx_destroy", "wf_schedule_default", "wf_solve", "wf_rfft2",
            "wf_irfft2", "wf_ctx_set_profiling", "wf_supported", "wf_strerror", "wf_tile_count",
            "wf_ctx_set_tile", "wf_ctx_get_tile", "wf_inverse_noise_weight", "wf_solve_batch",
-           "wf_solve_noalloc", "wf_noalloc_scratch_bytes", "wf_solve_refined")
+           "wf_solve_noalloc", "wf_noalloc_scratch_bytes", "wf_solve_refined", "wf_autotune")
 
 
 def load():
@@ -115,6 +115,9 @@ def load():
                                      ctypes.POINTER(_Schedule), i32, ctypes.c_double, vp,
                                      ctypes.POINTER(_Report), ctypes.POINTER(ctypes.c_double), vp]
     lib.wf_solve_refined.restype = i32
+    lib.wf_autotune.argtypes = [vp, ctypes.POINTER(_Inputs), i32, vp,
+                                ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i32), vp]
+    lib.wf_autotune.restype = i32
     lib.wf_rfft2.argtypes = [vp, vp, vp, vp]
     lib.wf_rfft2.restype = i32
     lib.wf_irfft2.argtypes = [vp, vp, vp, vp]
@@ -254,6 +257,31 @@ class Context:
         if st != 0:
             raise WFError(st, "wf_ctx_set_tile")
         return True
+
+    def autotune(self, d, s_k, n_pix, p_oof=None, p_stripe=None, mask=None, *, sweeps=48):
+        """``wf_autotune``: time a short solve of this map in every built
+        tiling and keep the fastest.  Returns {tiling: ms per probe solve}."""
+        import torch
+        lib = load()
+        ny, nx = self.ny, self.nx
+        nh = nx // 2 + 1
+        self._check(d, (ny, nx), "d")
+        self._check(s_k, (ny, nh), "s_k")
+        self._check(n_pix, (ny, nx), "n_pix")
+        self._check(p_oof, (ny, nh), "p_oof")
+        self._check(p_stripe, (ny,), "p_stripe")
+        self._check(mask, (ny, nx), "mask", torch.uint8)
+        scratch = torch.empty((ny, nx), dtype=self.dtype, device=self.device)
+        n = lib.wf_tile_count()
+        ms = (ctypes.c_double * n)()
+        best = ctypes.c_int32()
+        inp = _inputs(d, s_k, n_pix, p_oof, p_stripe, mask)
+        with torch.cuda.device(self.device):
+            st = lib.wf_autotune(self._h, ctypes.byref(inp), int(sweeps), scratch.data_ptr(), ms,
+                                 ctypes.byref(best), _stream_ptr(torch, self.device))
+        if st < 0:
+            raise WFError(st, "wf_autotune")
+        return {i: ms[i] for i in range(n) if ms[i] >= 0}
 
     def _check(self, t, shape, name, dtype=None):
         import torch

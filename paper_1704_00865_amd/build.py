@@ -17,10 +17,11 @@ INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libwf.so")
 BUILD_DIR = os.path.join(PKG, "_build")
 
-# (source, object, extra defines): the sweep kernels are compiled in two
-# parts, float32 and float64, in parallel
+# (source, object, extra defines): the sweep kernels are compiled in three
+# parts in parallel (float32 default tiling, float64, float32 other tilings)
 SOURCES = [("wf_kernels.hip", "wf_kernels_f32.o", ("WF_PART=1",)),
            ("wf_kernels.hip", "wf_kernels_f64.o", ("WF_PART=2",)),
+           ("wf_kernels.hip", "wf_kernels_tuned.o", ("WF_PART=4",)),
            ("wf_runtime.cpp", "wf_runtime.o", ()),
            ("wf_nn.hip", "wf_nn.o", ())]
 

@@ -37,11 +37,12 @@
 #include "wf_fft.hpp"
 #include "wf_kernels.hpp"
 
-// The build compiles this file twice, with WF_PART = 1 (float32 kernels and
-// the precision-free ones) and WF_PART = 2 (float64 kernels), so that the two
-// halves compile in parallel; without a definition both are built.
+// The build compiles this file three times, with WF_PART = 1 (float32
+// kernels in the default tiling and the precision-free ones), 2 (float64
+// kernels) and 4 (float32 kernels in the other tilings), so that the parts
+// compile in parallel; without a definition everything is built.
 #ifndef WF_PART
-#define WF_PART 3
+#define WF_PART 7
 #endif
 
 namespace wf {

@@ -11,6 +11,7 @@
 // result identical whatever the run-ahead.
 #include <hip/hip_runtime.h>
 
+#include <chrono>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -142,6 +143,10 @@ bool length_ok(int n, int prec) {
   const int hi = prec == WF_F64 ? 2048 : 4096;
   return n >= 64 && n <= hi && (n & (n - 1)) == 0;
 }
+
+// lengths whose float32 kernels are built in every tiling (the others have
+// the default tiling only)
+bool tuned_length(int n) { return n == 256 || n == 768 || n == 1536 || n == 2048; }
 
 int supported(int ny, int nx, int prec) {
   if (prec != WF_F32 && prec != WF_F64) return 0;
@@ -1324,13 +1329,65 @@ wf_status wf_ctx_set_tile(void* ctx, int32_t tile) {
   Ctx* c = (Ctx*)ctx;
   if (!c || tile < 0 || tile >= kNumTiles) return WF_EINVAL;
   // the default tiling is built for every size; the others for float32
-  // 2048 x 2048 maps only
-  const bool built = tile == kTileDefault || (c->prec == WF_F32 && c->nx == 2048 && c->ny == 2048);
+  // maps whose sides are both tuned lengths
+  const bool built = tile == kTileDefault || (c->prec == WF_F32 && tuned_length(c->nx) &&
+                                               tuned_length(c->ny));
   if (!built) return WF_EUNSUPPORTED;
   const TileCfg& t = kTiles[tile];
   if (c->ny % t.TR != 0 || (c->nx / 2) % t.TC != 0) return WF_EUNSUPPORTED;
   c->tile = tile;
   return WF_OK;
+}
+
+wf_status wf_autotune(void* ctx, const wf_inputs* in, int32_t sweeps, void* scratch,
+                      double* ms, int32_t* best, hipStream_t stream) {
+  Ctx* c = (Ctx*)ctx;
+  if (!c || !in || !scratch || sweeps < 1 || sweeps > 4096) return WF_EINVAL;
+  if (!in->d || !in->s_k || !in->n_pix) return WF_EINVAL;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev != c->device) return WF_EINVAL;
+  // a cooling ramp from 1e3 over the probe's first half (the sweep kernels
+  // do not depend on lambda's value; this keeps the probe a valid solve)
+  std::vector<double> lam(sweeps);
+  for (int k = 0; k < sweeps; ++k)
+    lam[k] = k < sweeps / 2 ? std::pow(1.0e3, 1.0 - 2.0 * k / sweeps) : 1.0;
+  wf_schedule sch;
+  wf_schedule_default(&sch);
+  sch.kind = WF_SCHED_FIXED;
+  sch.lambda = lam.data();
+  sch.n_lambda = sweeps;
+  sch.rtol = 0.0;
+  sch.max_sweeps = sweeps;
+  sch.monitor_every = std::min(16, (int)sweeps);
+  const int old_tile = c->tile, old_prof = c->profiling;
+  c->profiling = 0;
+  double best_ms = INFINITY;
+  int best_tile = -1;
+  wf_status err = WF_OK;
+  for (int tile = 0; tile < kNumTiles; ++tile) {
+    if (ms) ms[tile] = -1.0;
+    if (wf_ctx_set_tile(ctx, tile) != WF_OK) continue;
+    wf_status st = wf_solve(ctx, in, &sch, nullptr, scratch, nullptr, nullptr, stream);  // warm-up
+    const auto t0 = std::chrono::steady_clock::now();
+    for (int rep = 0; rep < 2 && st >= 0; ++rep)
+      st = wf_solve(ctx, in, &sch, nullptr, scratch, nullptr, nullptr, stream);
+    const double t =
+        std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count() /
+        2.0;
+    if (st < 0) {
+      err = st;
+      break;
+    }
+    if (ms) ms[tile] = t;
+    if (t < best_ms) {
+      best_ms = t;
+      best_tile = tile;
+    }
+  }
+  c->profiling = old_prof;
+  c->tile = (err == WF_OK && best_tile >= 0) ? best_tile : old_tile;
+  if (best) *best = c->tile;
+  return err;
 }
 
 int32_t wf_ctx_get_tile(void* ctx) {

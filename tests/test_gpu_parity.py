@@ -401,11 +401,14 @@ def test_bitwise_deterministic(gpu_lib):
     np.testing.assert_array_equal(ta, tb)
 
 
-def test_tilings_give_identical_results(gpu_lib):
+@pytest.mark.parametrize("shape", [(2048, 2048), (1536, 768), (256, 256)])
+def test_tilings_give_identical_results(gpu_lib, shape):
     """Every transit-buffer tiling only moves data differently, so all of
-    them must give bit-identical sweeps (2048x2048, float32)."""
-    p = synth.named_config("c3")
-    ctx = gpu_lib.Context(2048, 2048, "f32")
+    them must give bit-identical sweeps (float32; the tuned lengths)."""
+    ny, nx = shape
+    p = synth.named_config("c3") if shape == (2048, 2048) else synth.make_problem(ny, nx, 24,
+                                                                                   mask_frac=0.1)
+    ctx = gpu_lib.Context(ny, nx, "f32")
     args = _tensors(p, "f32")
     sched = gpu_lib.Schedule(lambdas=[1e4, 3e3, 1e3, 300.0, 100.0, 30.0], rtol=0.0,
                              max_sweeps=6, monitor_every=3)
@@ -427,6 +430,26 @@ def test_tilings_give_identical_results(gpu_lib):
             # only their summation order differs
             np.testing.assert_allclose(trace[:, 5], ref[1][:, 5], rtol=1e-12)
     assert n_built >= 2
+
+
+def test_autotuner_times_every_built_tiling_and_keeps_the_fastest(gpu_lib):
+    p = synth.make_problem(768, 1536, 25, mask_frac=0.1)
+    ctx = gpu_lib.Context(768, 1536, "f32")
+    args = _tensors(p, "f32")
+    times = ctx.autotune(*args, sweeps=16)
+    print("  tilings:", {k: round(v, 3) for k, v in times.items()}, flush=True)
+    assert len(times) == gpu_lib.load().wf_tile_count()  # all built at these lengths
+    assert ctx.tile == min(times, key=times.get)
+    ctx64 = gpu_lib.Context(256, 256, "f64")
+    q = synth.make_problem(256, 256, 26)
+    t64 = ctx64.autotune(*_tensors(q, "f64"), sweeps=8)
+    assert list(t64) == [1] and ctx64.tile == 1  # float64: the default tiling only
+    # the tuned context still matches the oracle
+    lams = list(_ramp(10, 20))
+    s_gpu, rep, trace = ctx.solve(*args, schedule=gpu_lib.Schedule(
+        lambdas=lams, rtol=0.0, max_sweeps=20, monitor_every=8))
+    res = oracle.solve(p, oracle.FixedSchedule(lams), max_sweeps=20, monitor_every=8)
+    _assert_parity(s_gpu.cpu().numpy().astype(np.float64), res.s, "f32")
 
 
 def test_converged_c2_field_matches_converged_oracle(gpu_lib):
