@@ -1035,13 +1035,15 @@ __global__ __launch_bounds__(kTCM * (NY / mon_elems<NY>())) void mon_col_kernel(
 }
 
 template <class T, int NX>
-__global__ __launch_bounds__(kTRM * (NX / mon_elems<NX>())) void mon_row_kernel(const MonArgs<T>* __restrict__ argv, int mode) {
+__global__ __launch_bounds__(kRWM * (NX / mon_elems<NX>())) void mon_row_kernel(const MonArgs<T>* __restrict__ argv, int mode) {
   const MonArgs<T>& m = argv[blockIdx.y];
   WF_GLOBAL T* s_out = gmem((T*)m.s_out);
   constexpr int E = mon_elems<NX>();
   constexpr int NT = NX / E;
   constexpr int KPm = KP<NX, kTCM>::value;
-  constexpr int BANDm = kTRM * KPm;
+  constexpr int GM = KPm / kTCM;          // tiles per tile row
+  constexpr int TRTC = kTRM * kTCM;
+  constexpr int BANDm = kRWM * KPm;      // values of this block's rows, per field
   // the two bands are staged row-major, X rows then Y rows, with a row stride
   // of 8 mod 16 values (rows 32 banks apart for 16-byte values, 16 for 8-byte
   // ones): reading a row's consecutive k_x and writing a tile's rows are then
@@ -1049,28 +1051,36 @@ __global__ __launch_bounds__(kTRM * (NX / mon_elems<NX>())) void mon_row_kernel(
   constexpr int RSm = KPm + ((8 - KPm % 16) + 16) % 16;
   using LM = ldsmap<T, NX, E>;  // exchange-buffer index map
   constexpr int XS = LM::size;
-  constexpr int LDSN = (2 * kTRM * RSm > kTRM * XS) ? 2 * kTRM * RSm : kTRM * XS;
+  constexpr int LDSN = (2 * kRWM * RSm > kRWM * XS) ? 2 * kRWM * RSm : kRWM * XS;
   __shared__ __align__(16) cx<T> lds[LDSN];
   constexpr bool LTW = lds_twiddles<T, NX>();
   __shared__ cx<T> twl[LTW ? NX : 1];
   __shared__ double sh[32];
   double lamv = 0.0;
   if (mode == MON_RESIDUAL && !monitor_active(gmem(m.sch), &lamv, gmem(m.lam))) return;
-  const int tid = threadIdx.x, band = blockIdx.x;
-  const WF_GLOBAL cx<T>* gx = gmem((const cx<T>*)m.Mx) + (size_t)band * BANDm;
-  const WF_GLOBAL cx<T>* gy = gmem((const cx<T>*)m.My) + (size_t)band * BANDm;
+  // a block takes kRWM rows of a kTRM-row tile row; the kTRM / kRWM
+  // blocks of one tile row share its HBM lines, so they run on one XCD
+  const int tid = threadIdx.x;
+  const int band = xcd_remap(blockIdx.x, gridDim.x, kTRM / kRWM);
+  const int y0 = band * kRWM;
+  const size_t tile_row = (size_t)(y0 / kTRM) * GM * TRTC + (y0 % kTRM) * kTCM;
+  const WF_GLOBAL cx<T>* gx = gmem((const cx<T>*)m.Mx) + tile_row;
+  const WF_GLOBAL cx<T>* gy = gmem((const cx<T>*)m.My) + tile_row;
   const WF_GLOBAL cx<T>* twg = gmem((const cx<T>*)m.twx);
   // the two bands' loads and the twiddle table's, all issued before the
-  // first LDS write
-  constexpr int NTHR = kTRM * NT;
+  // first LDS write; value e of the band is row rr, column g kTCM + cc with
+  // g = e / (kRWM kTCM): each tile holds kRWM kTCM consecutive values of it
+  constexpr int NTHR = kRWM * NT;
   constexpr int NB = (BANDm + NTHR - 1) / NTHR;
   cx<T> bx[NB], by[NB];
 #pragma unroll
   for (int i = 0; i < NB; ++i) {
     const int e = tid + i * NTHR;
     if (e < BANDm) {
-      bx[i] = ldc(gx + e);
-      by[i] = ldc(gy + e);
+      const int g = e / (kRWM * kTCM), w = e - g * (kRWM * kTCM);
+      const size_t off = (size_t)g * TRTC + w;
+      bx[i] = ldc(gx + off);
+      by[i] = ldc(gy + off);
     }
   }
   TwiddleStage<T, NX, E, NTHR> tws;
@@ -1079,11 +1089,10 @@ __global__ __launch_bounds__(kTRM * (NX / mon_elems<NX>())) void mon_row_kernel(
   for (int i = 0; i < NB; ++i) {
     const int e = tid + i * NTHR;
     if (e < BANDm) {
-      // tile order [kx / kTCM][row][kx % kTCM]
-      const int g = e / (kTRM * kTCM), w = e - g * (kTRM * kTCM);
+      const int g = e / (kRWM * kTCM), w = e - g * (kRWM * kTCM);
       const int rr = w / kTCM, kx = g * kTCM + (w - rr * kTCM);
       lds[rr * RSm + kx] = bx[i];
-      lds[(kTRM + rr) * RSm + kx] = by[i];
+      lds[(kRWM + rr) * RSm + kx] = by[i];
     }
   }
   if constexpr (LTW) tws.store(twl, tid);
@@ -1096,7 +1105,7 @@ __global__ __launch_bounds__(kTRM * (NX / mon_elems<NX>())) void mon_row_kernel(
     const bool hi = k > NX / 2;
     const int kx = hi ? NX - k : k;
     const int li = r * RSm + kx;
-    cx<T> X = lds[li], Y = lds[kTRM * RSm + li];
+    cx<T> X = lds[li], Y = lds[kRWM * RSm + li];
     if (kx == 0 || kx == NX / 2) {
       X.im = (T)0;
       Y.im = (T)0;
@@ -1113,7 +1122,7 @@ __global__ __launch_bounds__(kTRM * (NX / mon_elems<NX>())) void mon_row_kernel(
   const WF_GLOBAL T* mn2 = gmem(m.nbar2);
   const WF_GLOBAL T* mnp = gmem(m.npix);
   const WF_GLOBAL T* md = gmem(m.d);
-  const int y = band * kTRM + r;
+  const int y = y0 + r;
   double a_dd = 0.0, a_mx = 0.0;
 #pragma unroll
   for (int q = 0; q < E; ++q) {

@@ -7,9 +7,11 @@
 
 namespace wf {
 
-// tile of the float64 monitor transit buffers
-constexpr int kTRM = 2;
+// tile of the monitor's transit buffers (kTRM rows x kTCM columns: 128
+// contiguous bytes in float32), and the rows one monitor row block takes
+constexpr int kTRM = 8;
 constexpr int kTCM = 2;
+constexpr int kRWM = 2;
 
 // Fourier side of the messenger chain (levels between the signal and the
 // pixel-space white level)

@@ -113,7 +113,7 @@ void for_each_buffer(Ctx* c, F take) {
   take((void**)&c->twy, ny * 2 * esz);
   take((void**)&c->Mx, ny * c->kpm * 2 * esz);
   take((void**)&c->My, ny * c->kpm * 2 * esz);
-  take((void**)&c->part, std::max<size_t>(2 * ny / kTRM, 16 * kStatBlocks) * sizeof(double));
+  take((void**)&c->part, std::max<size_t>(2 * ny / kRWM, 16 * kStatBlocks) * sizeof(double));
   // at most ny/2 row blocks and nx/4 column blocks (every tiling has at
   // least 2 rows per row block and 2 columns per tile)
   take((void**)&c->jpart, (ny / 2 + nx / 4) * sizeof(double));
@@ -522,7 +522,7 @@ wf_status map_setup(Ctx* c, const wf_inputs* in, const wf_schedule* s, const voi
   r.m.sch = dsched;
   r.m.s_out = s_out;
   r.m.out_chain = s->field_mode;
-  r.ctrl = CtrlArgs{dsched, c->lam, c->part, c->ny / kTRM, c->trace, c->jpart, j_blocks(c)};
+  r.ctrl = CtrlArgs{dsched, c->lam, c->part, c->ny / kRWM, c->trace, c->jpart, j_blocks(c)};
   // initial state (the single-map argument block is used for the warm start)
   const size_t modes_b = (size_t)c->nh * c->ny * 2 * c->esz;
   if (s_init) {
@@ -1003,7 +1003,7 @@ wf_status solve_refined(Ctx* c32, Ctx* c64, const wf_inputs* in, const wf_schedu
     // float64 residual of x_acc; its negative is the next right-hand side
     WF_TRY(launch_mon_col<double>(mh[0], dm, 1, MON_REFINE, st));
     WF_TRY(launch_mon_row<double>(mh[0], dm, 1, MON_REFINE, st));
-    WF_TRY(launch_pair_sum(c64->part, (int)(ny / kTRM), c64->stats, st));
+    WF_TRY(launch_pair_sum(c64->part, (int)(ny / kRWM), c64->stats, st));
     WF_TRY(hipMemcpyAsync(c64->h_stats, c64->stats, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
     WF_TRY(hipStreamSynchronize(st));
     dd2 = c64->h_stats[0];
