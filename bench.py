@@ -94,6 +94,10 @@ def _args():
     ap.add_argument("--skip-batch", action="store_true")
     ap.add_argument("--skip-warm", action="store_true")
     ap.add_argument("--skip-sec4", action="store_true")
+    ap.add_argument("--ttr-paths", default="all",
+                    help="comma-separated time-to-1e-6 entries to run (default all): "
+                         "f64_shrink0.97, f64_shrink0.9, f64_paper_recipe, f32_refined, "
+                         "f64_stop_full")
     ap.add_argument("--warm-size", type=int, default=256)
     ap.add_argument("--warm-train", type=int, default=512)
     ap.add_argument("--warm-test", type=int, default=16)
@@ -227,7 +231,7 @@ def bench_batch(wf, synth, torch, dev, a):
                     f"{a.monitor_every} sweeps is extra work inside the time)"}
 
 
-def bench_time_to_rtol(wf, torch, dev, p, n, mask, tile32):
+def bench_time_to_rtol(wf, torch, dev, p, n, mask, tile32, paths=None):
     """Zero-start solves of the same map to rho <= 1e-6 (augmented chain).
 
     float64 throughout: adaptive cooling from 1e4 with lambda <- lambda^0.97
@@ -264,8 +268,13 @@ def bench_time_to_rtol(wf, torch, dev, p, n, mask, tile32):
               f"rho {rep['rho']:.2e}, rho_mask {rep['rho_mask']:.2e}, {rep['status']}",
               file=sys.stderr, flush=True)
 
+    def want(name):
+        return paths is None or name in paths
+
     for name, lam0, shrink in (("f64_shrink0.97", 1.0e4, 0.97), ("f64_shrink0.9", 1.0e4, 0.9),
                                ("f64_paper_recipe", 1.0e6, 0.7)):
+        if not want(name):
+            continue
         sch = wf.Schedule(lambda0=lam0, shrink=shrink, rtol=1e-6, max_sweeps=100000,
                           monitor_every=16, chain="augmented")
         torch.cuda.synchronize()
@@ -278,6 +287,22 @@ def bench_time_to_rtol(wf, torch, dev, p, n, mask, tile32):
                         chain="augmented")
     corr = wf.Schedule(lambda0=30.0, shrink=0.9, rtol=0.1, max_sweeps=30000, monitor_every=16,
                        chain="augmented")
+    if want("f32_refined"):
+        bench_refined(wf, torch, ctx32, ctx64, args64, out64, first, corr, entry)
+    if want("f64_stop_full"):
+        bench_stop_full(wf, torch, ctx64, args64, out64, entry)
+    ok = {k: v for k, v in out.items() if v["status"] == "OK" and k != "f64_stop_full"}
+    if ok:
+        best = min(ok, key=lambda k: ok[k]["seconds"])
+        out["best"] = {"path": best, "seconds": ok[best]["seconds"], "rho": ok[best]["rho"],
+                       "rho_mask": ok[best]["rho_mask"]}
+    ctx64.close()
+    ctx32.close()
+    return out
+
+
+def bench_refined(wf, torch, ctx32, ctx64, args64, out64, first, corr, entry):
+    """float32 sweeps refined by float64 residuals (wf_solve_refined)."""
     wf.solve_refined(ctx32, ctx64, *args64, first=first, corr=corr, max_rounds=4, rtol=1e-6,
                      out=out64)
     torch.cuda.synchronize()
@@ -290,6 +315,10 @@ def bench_time_to_rtol(wf, torch, dev, p, n, mask, tile32):
           per_round=[{"sweeps_so_far": int(t[1]), "rho": t[2]} for t in tr3],
           first={"lambda0": 1e4, "shrink": 0.9, "rtol": 1e-4},
           correction={"lambda0": 30.0, "shrink": 0.9, "rtol": 0.1}, monitor_every=16)
+
+
+def bench_stop_full(wf, torch, ctx64, args64, out64, entry):
+    """float64 with the masked part in the stop test, bounded budget."""
     sch = wf.Schedule(lambda0=1.0e4, shrink=0.97, rtol=1e-6, max_sweeps=40000, monitor_every=16,
                       chain="augmented", stop_full=True)
     torch.cuda.synchronize()
@@ -298,14 +327,6 @@ def bench_time_to_rtol(wf, torch, dev, p, n, mask, tile32):
     torch.cuda.synchronize()
     entry("f64_stop_full", r4, time.perf_counter() - t1, 8, dtype="f64", lambda0=1e4,
           shrink=0.97, stop="hypot(rho, rho_mask) <= 1e-6, budget 40000 sweeps")
-    ok = {k: v for k, v in out.items() if v["status"] == "OK" and k != "f64_stop_full"}
-    if ok:
-        best = min(ok, key=lambda k: ok[k]["seconds"])
-        out["best"] = {"path": best, "seconds": ok[best]["seconds"], "rho": ok[best]["rho"],
-                       "rho_mask": ok[best]["rho_mask"]}
-    ctx64.close()
-    ctx32.close()
-    return out
 
 
 def bench_section4(wf, torch, dev, p, n):
@@ -521,7 +542,8 @@ def main():
 
     ttr = None
     if not a.skip_ttr:
-        ttr = bench_time_to_rtol(wf, torch, dev, p, n, args[5], ctx.tile)
+        ttr = bench_time_to_rtol(wf, torch, dev, p, n, args[5], ctx.tile,
+                                 None if a.ttr_paths == "all" else set(a.ttr_paths.split(",")))
 
     sec4 = None
     if not a.skip_sec4:
