@@ -1,9 +1,9 @@
-// Workgroup FFTs for gfx950: radix-16/8/4 Stockham passes with the data in
+// Workgroup FFTs for gfx950: radix-16/12/8/4/2 Stockham passes with the data in
 // registers and one LDS exchange between passes.
 //
 // A transform of length N (a power of two from 64 to 4096, or 3 times one:
 // 384, 768, 1536) is spread over NT = N/E threads that each hold E complex
-// values (E = 16, or 24 when N has a factor 3).  Register q of thread t holds
+// values (E = 16, or 12 when N has a factor 3).  Register q of thread t holds
 // element t + NT*q both before the first pass and after the last one (natural
 // order), so a transform can be followed by per-element work and by another
 // transform without any reshuffle, and its first loads and last stores are
@@ -11,7 +11,7 @@
 // computes, for butterfly i in [0, N/R):
 //     u_m = x[i + m N/R] * w_{pR}^{m (i mod p)},  U = DFT_R(u),
 //     y[(i - i mod p) R + (i mod p) + m p] = U_m,
-// the autosorting Stockham form (radix 16, 8, 4, 3).  Twiddles w_N^j come from a table built in
+// the autosorting Stockham form (radix 16, 12, 8, 4, 2).  Twiddles w_N^j come from a table built in
 // double precision on the host and rounded once (no device sin/cos).
 #pragma once
 
@@ -163,20 +163,56 @@ __device__ __forceinline__ void dft3(cx<T>* u) {
   u[2] = m - r;
 }
 
+// 12 = 3 (n1) x 4 (n2): n = 4 n1 + n2, k = k1 + 3 k2.  Three-point DFTs over
+// n1, twiddles w_12^(n2 k1), four-point DFTs over n2.
+template <class T, bool INV>
+__device__ __forceinline__ void dft12(cx<T>* u) {
+  const T h = (T)0.5, r3 = (T)0.86602540378443864676;  // cos 60, sin 60 degrees
+  cx<T> y[4][3];
+#pragma unroll
+  for (int n2 = 0; n2 < 4; ++n2) {
+    y[n2][0] = u[n2];
+    y[n2][1] = u[4 + n2];
+    y[n2][2] = u[8 + n2];
+    dft3<T, INV>(y[n2]);
+  }
+  // w_12^j for j = 1, 2, 4 (forward: exp(-i pi j / 6)); j = 3 is -+i, j = 6 is -1
+  const T sg = INV ? (T)1 : (T)-1;
+  const cx<T> w1 = {r3, sg * h}, w2 = {h, sg * r3}, w4 = {-h, sg * r3};
+  y[1][1] = cmul(y[1][1], w1);
+  y[1][2] = cmul(y[1][2], w2);
+  y[2][1] = cmul(y[2][1], w2);
+  y[2][2] = cmul(y[2][2], w4);
+  y[3][1] = mul_w4<T, INV>(y[3][1]);
+  y[3][2] = cx<T>{-y[3][2].re, -y[3][2].im};
+#pragma unroll
+  for (int k1 = 0; k1 < 3; ++k1) {
+    cx<T> a0 = y[0][k1], a1 = y[1][k1], a2 = y[2][k1], a3 = y[3][k1];
+    dft4<T, INV>(a0, a1, a2, a3);
+    u[k1] = a0;
+    u[k1 + 3] = a1;
+    u[k1 + 6] = a2;
+    u[k1 + 9] = a3;
+  }
+}
+
 template <class T, int R, bool INV>
 __device__ __forceinline__ void dft(cx<T>* u) {
   if constexpr (R == 2) dft2<T, INV>(u);
   else if constexpr (R == 3) dft3<T, INV>(u);
   else if constexpr (R == 4) dft4<T, INV>(u);
   else if constexpr (R == 8) dft8<T, INV>(u);
+  else if constexpr (R == 12) dft12<T, INV>(u);
   else if constexpr (R == 16) dft16<T, INV>(u);
 }
 
-// complex values held by each thread: 16 for powers of two, 24 for lengths
-// with a factor 3 (so that both radix 8 and radix 3 divide it)
+// complex values held by each thread: 16 for powers of two, 12 for lengths
+// with a factor 3 (radices 4, 2 and 12 divide it; with 24 values and radix 8
+// a 1536-point transform filled one wave, whose 12 KB exchange buffer held
+// the kernels to 1.5-2 waves per SIMD)
 template <int N>
 struct elems {
-  static constexpr int value = (N % 3 == 0) ? 24 : 16;
+  static constexpr int value = (N % 3 == 0) ? 12 : 16;
 };
 
 // Index map of one transform's LDS exchange buffer (N complex values, E per
@@ -200,20 +236,20 @@ struct ldsmap {
   }
 };
 
-// radix plan R0 * R1 * R2 * R3 = N (1 = no pass); a radix-3 pass comes last
-// so every earlier span is a power of two
+// radix plan R0 * R1 * R2 * R3 * R4 = N (1 = no pass); the radix-12 pass of
+// the lengths with a factor 3 comes last, so every earlier span is a power of two
 template <int N>
 struct plan;
-template <> struct plan<64> { static constexpr int r[4] = {16, 4, 1, 1}; };
-template <> struct plan<128> { static constexpr int r[4] = {16, 8, 1, 1}; };
-template <> struct plan<256> { static constexpr int r[4] = {16, 16, 1, 1}; };
-template <> struct plan<512> { static constexpr int r[4] = {16, 8, 4, 1}; };
-template <> struct plan<1024> { static constexpr int r[4] = {16, 16, 4, 1}; };
-template <> struct plan<2048> { static constexpr int r[4] = {16, 16, 8, 1}; };
-template <> struct plan<4096> { static constexpr int r[4] = {16, 16, 16, 1}; };
-template <> struct plan<384> { static constexpr int r[4] = {8, 4, 4, 3}; };
-template <> struct plan<768> { static constexpr int r[4] = {8, 8, 4, 3}; };
-template <> struct plan<1536> { static constexpr int r[4] = {8, 8, 8, 3}; };
+template <> struct plan<64> { static constexpr int r[5] = {16, 4, 1, 1, 1}; };
+template <> struct plan<128> { static constexpr int r[5] = {16, 8, 1, 1, 1}; };
+template <> struct plan<256> { static constexpr int r[5] = {16, 16, 1, 1, 1}; };
+template <> struct plan<512> { static constexpr int r[5] = {16, 8, 4, 1, 1}; };
+template <> struct plan<1024> { static constexpr int r[5] = {16, 16, 4, 1, 1}; };
+template <> struct plan<2048> { static constexpr int r[5] = {16, 16, 8, 1, 1}; };
+template <> struct plan<4096> { static constexpr int r[5] = {16, 16, 16, 1, 1}; };
+template <> struct plan<384> { static constexpr int r[5] = {4, 4, 2, 12, 1}; };
+template <> struct plan<768> { static constexpr int r[5] = {4, 4, 4, 12, 1}; };
+template <> struct plan<1536> { static constexpr int r[5] = {4, 4, 4, 2, 12}; };
 
 constexpr int kE = 16;  // values per thread for power-of-two lengths
 
@@ -221,11 +257,12 @@ constexpr int kE = 16;  // values per thread for power-of-two lengths
 // plan, or (E = 8) radices of at most 8
 template <int N, int E>
 struct plan_for {
-  static constexpr int r0 = plan<N>::r[0], r1 = plan<N>::r[1], r2 = plan<N>::r[2], r3 = plan<N>::r[3];
+  static constexpr int r0 = plan<N>::r[0], r1 = plan<N>::r[1], r2 = plan<N>::r[2], r3 = plan<N>::r[3],
+                       r4 = plan<N>::r[4];
 };
-template <> struct plan_for<1024, 8> { static constexpr int r0 = 8, r1 = 8, r2 = 4, r3 = 4; };
-template <> struct plan_for<2048, 8> { static constexpr int r0 = 8, r1 = 8, r2 = 8, r3 = 4; };
-template <> struct plan_for<4096, 8> { static constexpr int r0 = 8, r1 = 8, r2 = 8, r3 = 8; };
+template <> struct plan_for<1024, 8> { static constexpr int r0 = 8, r1 = 8, r2 = 4, r3 = 4, r4 = 1; };
+template <> struct plan_for<2048, 8> { static constexpr int r0 = 8, r1 = 8, r2 = 8, r3 = 4, r4 = 1; };
+template <> struct plan_for<4096, 8> { static constexpr int r0 = 8, r1 = 8, r2 = 8, r3 = 8, r4 = 1; };
 
 // Twiddle tables.  The natural table holds w_N^j (forward sign) at j; pass
 // (span P, radix R) reads it at j = m k N/(P R), so that the lanes of one read
@@ -237,10 +274,11 @@ template <> struct plan_for<4096, 8> { static constexpr int r0 = 8, r1 = 8, r2 =
 template <int N, int E>
 struct twp_offsets {
   using PL = plan_for<N, E>;
-  static constexpr int p1 = PL::r0, p2 = p1 * PL::r1, p3 = p2 * PL::r2;
+  static constexpr int p1 = PL::r0, p2 = p1 * PL::r1, p3 = p2 * PL::r2, p4 = p3 * PL::r3;
   static constexpr int o2 = 0;                             // pass 2 (span p1)
   static constexpr int o3 = o2 + (PL::r1 - 1) * p1;        // pass 3 (span p2)
   static constexpr int o4 = o3 + (PL::r2 - 1) * p2;        // pass 4 (span p3)
+  static constexpr int o5 = o4 + (PL::r3 - 1) * p3;        // pass 5 (span p4)
   static constexpr int size = N - p1;
 };
 
@@ -256,8 +294,12 @@ __device__ __forceinline__ int twp_source(int e) {
     const int o = e - O::o3, m = 1 + o / O::p2, k = o - (m - 1) * O::p2;
     return m * k * (N / (O::p2 * PL::r2));
   }
-  const int o = e - O::o4, m = 1 + o / O::p3, k = o - (m - 1) * O::p3;
-  return m * k * (N / (O::p3 * PL::r3));
+  if (e < O::o5) {
+    const int o = e - O::o4, m = 1 + o / O::p3, k = o - (m - 1) * O::p3;
+    return m * k * (N / (O::p3 * PL::r3));
+  }
+  const int o = e - O::o5, m = 1 + o / O::p4, k = o - (m - 1) * O::p4;
+  return m * k * (N / (O::p4 * PL::r4));
 }
 
 // Staging of the pass-major table into LDS by NTHR threads, in two steps so
@@ -348,21 +390,29 @@ template <class T, int N, bool INV, int E = elems<N>::value, bool TWP = false,
 __device__ __forceinline__ void fft(cx<T>* reg, cx<T>* lds, int t, TW tw) {
   using PL = plan_for<N, E>;
   using O = twp_offsets<N, E>;
-  constexpr int R0 = PL::r0, R1 = PL::r1, R2 = PL::r2, R3 = PL::r3;
-  static_assert(R0 * R1 * R2 * R3 == N, "radix plan must multiply to N");
-  constexpr int F2 = TWP ? O::o2 : -1, F3 = TWP ? O::o3 : -1, F4 = TWP ? O::o4 : -1;
+  constexpr int R0 = PL::r0, R1 = PL::r1, R2 = PL::r2, R3 = PL::r3, R4 = PL::r4;
+  static_assert(R0 * R1 * R2 * R3 * R4 == N, "radix plan must multiply to N");
+  constexpr int F2 = TWP ? O::o2 : -1, F3 = TWP ? O::o3 : -1, F4 = TWP ? O::o4 : -1,
+                F5 = TWP ? O::o5 : -1;
+  constexpr int P2 = R0 * R1, P3 = P2 * R2, P4 = P3 * R3;
   if constexpr (R2 == 1) {
     stockham_pass<T, N, R0, 1, INV, false, E, -1, TW>(reg, lds, t, tw);
     stockham_pass<T, N, R1, R0, INV, true, E, F2, TW>(reg, lds, t, tw);
   } else if constexpr (R3 == 1) {
     stockham_pass<T, N, R0, 1, INV, false, E, -1, TW>(reg, lds, t, tw);
     stockham_pass<T, N, R1, R0, INV, false, E, F2, TW>(reg, lds, t, tw);
-    stockham_pass<T, N, R2, R0 * R1, INV, true, E, F3, TW>(reg, lds, t, tw);
+    stockham_pass<T, N, R2, P2, INV, true, E, F3, TW>(reg, lds, t, tw);
+  } else if constexpr (R4 == 1) {
+    stockham_pass<T, N, R0, 1, INV, false, E, -1, TW>(reg, lds, t, tw);
+    stockham_pass<T, N, R1, R0, INV, false, E, F2, TW>(reg, lds, t, tw);
+    stockham_pass<T, N, R2, P2, INV, false, E, F3, TW>(reg, lds, t, tw);
+    stockham_pass<T, N, R3, P3, INV, true, E, F4, TW>(reg, lds, t, tw);
   } else {
     stockham_pass<T, N, R0, 1, INV, false, E, -1, TW>(reg, lds, t, tw);
     stockham_pass<T, N, R1, R0, INV, false, E, F2, TW>(reg, lds, t, tw);
-    stockham_pass<T, N, R2, R0 * R1, INV, false, E, F3, TW>(reg, lds, t, tw);
-    stockham_pass<T, N, R3, R0 * R1 * R2, INV, true, E, F4, TW>(reg, lds, t, tw);
+    stockham_pass<T, N, R2, P2, INV, false, E, F3, TW>(reg, lds, t, tw);
+    stockham_pass<T, N, R3, P3, INV, false, E, F4, TW>(reg, lds, t, tw);
+    stockham_pass<T, N, R4, P4, INV, true, E, F5, TW>(reg, lds, t, tw);
   }
 }
 

@@ -357,11 +357,11 @@ constexpr int mon_elems() {
 }
 
 // at least 2 waves per SIMD so that two blocks share a CU and one
-// block's memory phase overlaps another's FFT; float64 transforms with 24
-// values per thread need the whole register file of one wave instead
+// block's memory phase overlaps another's FFT; 3 for the float32 lengths with
+// a factor 3 (12 values per thread)
 template <class T, int N>
 constexpr int min_waves() {
-  return (sizeof(T) == 8 && elems<N>::value == 24) ? 1 : 2;
+  return (sizeof(T) == 4 && N % 3 == 0) ? 3 : 2;
 }
 // waves per SIMD the column kernel is built for: four with 8 values per
 // thread, else as above
@@ -477,8 +477,10 @@ __global__ __launch_bounds__((RW / 2) * (NX / row_elems<T, NX>()), (min_waves<T,
       return;
     } else {
       // white-level update, data and coefficients loaded in batches of 8
-      // (float32) or 4 (float64) values, to stay within the register budget
-      constexpr int QB = sizeof(T) == 8 ? 4 : 8;
+      // (float32) or 4 (float64, or 12 values per thread) values, to stay
+      // within the register budget
+      constexpr int QB = (sizeof(T) == 8 || E % 8 != 0) ? 4 : 8;
+      static_assert(E % QB == 0, "batches split the thread's values evenly");
       const WF_GLOBAL T* gd = gmem(a.d);
       const WF_GLOBAL T* gn2 = gmem(a.nbar2);
 #pragma unroll
@@ -682,10 +684,13 @@ __global__ __launch_bounds__(TC * (NY / col_elems<T, NY>()), (col_min_waves<T, N
   constexpr int NTHR = TC * NT;  // threads of the block
 
   // per-mode state and coefficients of this column, loaded in batches of 8
-  // modes, or 4 where the registers are scarce (float64, 24 values per
-  // thread, or 4096 points; 8 spilled there), or 2 with 8 values per thread
-  // (four waves per SIMD leave 128 registers)
-  constexpr int HB = E == 8 ? 2 : ((sizeof(T) == 8 || E == 24 || NY >= 4096) ? 4 : 8);
+  // modes, or 4 where the registers are scarce (float64, or 4096 points; 8
+  // spilled there), or 2 with 8 values per thread (four waves per SIMD leave
+  // 128 registers) and with 12 float32 values (three waves, 168 registers)
+  constexpr int HB = (E == 8 || (E == 12 && sizeof(T) == 4))
+                         ? 2
+                         : ((sizeof(T) == 8 || E % 8 != 0 || NY >= 4096) ? 4 : 8);
+  static_assert(E % HB == 0, "batches split the thread's values evenly");
   constexpr bool hasA = FK != FK_NONE;
   constexpr bool hasB = FK == FK_ARRAY_STRIPE;
   constexpr bool needNb = FK == FK_ARRAY || FK == FK_ARRAY_STRIPE;
