@@ -23,8 +23,9 @@ Also printed, on the same JSON line:
                 one batched solve (shared launches, replayed HIP graph), against
                 the same maps solved one after the other
   warm_start    the learned warm start: a network trained in the run on solver
-                solutions of 256^2 maps, then sweeps to rho <= 1e-6 on held-out
-                maps from the zero start and from the network's prediction
+                solutions of 2 000 maps of 1024^2, then sweeps to rho <= 1e-6 on
+                200 held-out maps from the zero start and from the network's
+                prediction
   section4      the two further uses Section 4 names (inverse-noise weighting
                 with S = alpha I; projected Fourier modes), float64, to 1e-6
   cpu_baseline  the float64 CPU oracle on a bounded sample of sweeps, its time
@@ -98,10 +99,10 @@ def _args():
                     help="comma-separated time-to-1e-6 entries to run (default all): "
                          "f64_shrink0.97, f64_shrink0.9, f64_paper_recipe, f32_refined, "
                          "f64_stop_full")
-    ap.add_argument("--warm-size", type=int, default=256)
-    ap.add_argument("--warm-train", type=int, default=512)
-    ap.add_argument("--warm-test", type=int, default=16)
-    ap.add_argument("--warm-epochs", type=int, default=30)
+    ap.add_argument("--warm-size", type=int, default=1024)
+    ap.add_argument("--warm-train", type=int, default=2000)
+    ap.add_argument("--warm-test", type=int, default=200)
+    ap.add_argument("--warm-epochs", type=int, default=5)
     ap.add_argument("--batch-steps", type=int, default=2)
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain 1 GiB device copy (counter calibration)")
@@ -559,11 +560,19 @@ def main():
         n_w = a.warm_size
         trp, tep = warm_maps
         warm_maps = None
+        tw = time.perf_counter()
         warm = warmstart.experiment(trp, tep, epochs=a.warm_epochs, batch=16, lr=2e-3,
+                                    warm_lam0=(1e3,), target_precision="f32",
+                                    target_rtol=1e-4, target_lam0=1e4, target_shrink=0.9,
                                     log=lambda m: print(f"[bench] {m}", file=sys.stderr, flush=True))
+        warm["seconds_total"] = round(time.perf_counter() - tw, 1)
         warm["recipe"] = (f"{n_w}^2 maps, three noise terms, 10% disc mask; train seeds "
-                          f"10000-{10000 + a.warm_train - 1}, test seeds 20000-{20000 + a.warm_test - 1}; "
-                          "targets and evaluation: float64 augmented chain, field_mode 1")
+                          f"10000-{10000 + a.warm_train - 1}, held-out test seeds "
+                          f"20000-{20000 + a.warm_test - 1}; training targets: float32 augmented "
+                          "chain to rho 1e-4 (lambda^0.9 from 1e4); evaluation: float64 augmented "
+                          "chain to rho 1e-6 (lambda^0.97 from 1e4 for the zero start, from 1e3 "
+                          "for the network's start), field_mode 1")
+        trp = tep = None
 
     cpu = None
     if not a.skip_cpu:

@@ -156,21 +156,43 @@ def rel_error(a, b) -> np.ndarray:
     return (num / den).cpu().numpy()
 
 
+def _seeds(problems):
+    return [p.meta.get("seed") for p in problems if getattr(p, "meta", None)]
+
+
+def _seed_range(problems):
+    sd = _seeds(problems)
+    return [min(sd), max(sd)] if sd else None
+
+
 def experiment(train_problems: Sequence, test_problems: Sequence, *, precision: str = "f64",
                target_rtol: float = 1e-5, eval_rtol: float = 1e-6, lam0: float = 1e4,
                shrink: float = 0.97, warm_lam0: Sequence[float] = (1e3, 1e2, 10.0),
                epochs: int = 20, batch: int = 16,
-               lr: float = 2e-3, seed: int = 0, max_sweeps: int = 200000, log=None) -> dict:
+               lr: float = 2e-3, seed: int = 0, max_sweeps: int = 200000,
+               target_precision: str | None = None, target_lam0: float | None = None,
+               target_shrink: float | None = None, log=None) -> dict:
     """Train on solver solutions (chain fields u) of train_problems and
     compare sweeps to rho <= eval_rtol on test_problems from the zero start
     and from the network's prediction (for each lambda0 in warm_lam0), with
-    the converged field as a warm start for reference.  Augmented chain."""
+    the converged field as a warm start for reference.  Augmented chain.
+
+    The training targets may be solved in another precision and schedule
+    (target_*; the network is then trained and run in that precision and its
+    prediction converted).  The test maps must be held out: a seed shared
+    with the training maps raises ValueError."""
     import torch
+    shared = set(_seeds(train_problems)) & set(_seeds(test_problems))
+    if shared:
+        raise ValueError(f"test maps share seeds with the training maps: {sorted(shared)[:8]}")
+    tprec = precision if target_precision is None else target_precision
     h, w = train_problems[0].d.shape
     t0 = time.perf_counter()
-    tr = stack_problems(train_problems, precision)
+    tr = stack_problems(train_problems, tprec)
     te = stack_problems(test_problems, precision)
-    tsched = Schedule(lambda0=lam0, shrink=shrink, rtol=target_rtol, max_sweeps=max_sweeps,
+    tsched = Schedule(lambda0=lam0 if target_lam0 is None else target_lam0,
+                      shrink=shrink if target_shrink is None else target_shrink,
+                      rtol=target_rtol, max_sweeps=max_sweeps,
                       monitor_every=16, chain="augmented", chain_field=True)
     tr.s, rtr = solve_set(train_problems, tr, tsched, log=log)
     torch.cuda.synchronize()
@@ -178,25 +200,38 @@ def experiment(train_problems: Sequence, test_problems: Sequence, *, precision: 
     if log:
         log(f"training targets: {tr.n} solves in {t_gen:.1f} s, "
             f"{np.mean([r['sweeps'] for r in rtr]):.0f} sweeps each")
-    net = WarmNet(h, w, batch_max=max(batch, 8), precision=precision)
+    net = WarmNet(h, w, batch_max=max(batch, 8), precision=tprec)
     net.set_params(init_params(seed))
     t1 = time.perf_counter()
     hist = train(net, tr, epochs=epochs, batch=batch, lr=lr, lr_final=lr * 0.05, seed=seed, log=log)
     torch.cuda.synchronize()
     t_train = time.perf_counter() - t1
     steps = epochs * (tr.n // batch)
+    tr = None  # the training set is no longer needed
     # reference solutions of the test maps and the predictions
     esched = Schedule(lambda0=lam0, shrink=shrink, rtol=eval_rtol, max_sweeps=max_sweeps,
                       monitor_every=16, chain="augmented", chain_field=True)
+    t2 = time.perf_counter()
     s_ref, rzero = solve_set(test_problems, te, esched, log=log)
-    pred = predict(net, te, max(batch, 8))
+    torch.cuda.synchronize()
+    t_zero = time.perf_counter() - t2
+    if tprec == precision:
+        pred = predict(net, te, max(batch, 8))
+    else:
+        nd = torch.float32 if tprec == "f32" else torch.float64
+        pred = predict(net, MapSet(te.d.to(nd), te.n_pix.to(nd), te.mask), max(batch, 8))
+        pred = pred.to(te.d.dtype)
     err_pred = rel_error(pred, s_ref)
     err_zero = np.ones(te.n)
     e = (pred - s_ref).double()
     row = e.mean(dim=2, keepdim=True).expand_as(e)
     frac_rows = float((row.pow(2).sum() / e.pow(2).sum()).item())
-    res = {"maps_train": tr.n, "maps_test": te.n, "map": [h, w], "dtype": precision,
+    res = {"maps_train": len(train_problems), "maps_test": te.n, "map": [h, w],
+           "dtype": precision, "target_dtype": tprec,
+           "held_out": {"train_seeds": _seed_range(train_problems),
+                        "test_seeds": _seed_range(test_problems), "shared_seeds": 0},
            "chain": "augmented", "eval_rtol": eval_rtol, "target_rtol": target_rtol,
+           "target_sweeps_mean": float(np.mean([r["sweeps"] for r in rtr])),
            "gen_seconds": round(t_gen, 2), "train_seconds": round(t_train, 2), "train_steps": steps,
            "train_batch": batch, "epochs": epochs, "loss_first_epoch": hist[0],
            "train_step_ms": round(1e3 * t_train / max(steps, 1), 3),
@@ -209,16 +244,22 @@ def experiment(train_problems: Sequence, test_problems: Sequence, *, precision: 
            "pred_error_energy_in_row_means": frac_rows,
            "shrink": shrink,
            "zero": {"lambda0": lam0, "sweeps_mean": float(np.mean([r["sweeps"] for r in rzero])),
+                    "seconds": round(t_zero, 2),
                     "converged": int(sum(r["status"] == "OK" for r in rzero)),
                     "rel_error_start_median": float(np.median(err_zero))},
            "warm": []}
     for l0 in warm_lam0:
         sch = Schedule(lambda0=l0, shrink=shrink, rtol=eval_rtol, max_sweeps=max_sweeps,
                        monitor_every=16, chain="augmented", chain_field=True)
+        t3 = time.perf_counter()
         _, rw = solve_set(test_problems, te, sch, s_init=pred, log=log)
+        torch.cuda.synchronize()
+        ratio = [a["sweeps"] / max(b["sweeps"], 1) for a, b in zip(rzero, rw)]
         res["warm"].append({"lambda0": l0,
                             "sweeps_mean": float(np.mean([r["sweeps"] for r in rw])),
-                            "converged": int(sum(r["status"] == "OK" for r in rw))})
+                            "converged": int(sum(r["status"] == "OK" for r in rw)),
+                            "seconds": round(time.perf_counter() - t3, 2),
+                            "sweeps_ratio_per_map_median": float(np.median(ratio))})
         if log:
             log(f"warm lambda0={l0:g}: network {res['warm'][-1]['sweeps_mean']:.0f} sweeps, "
                 f"zero start {res['zero']['sweeps_mean']:.0f}")
@@ -230,5 +271,6 @@ def experiment(train_problems: Sequence, test_problems: Sequence, *, precision: 
     best = min(res["warm"], key=lambda r: (-r["converged"], r["sweeps_mean"]))
     res["best_warm_lambda0"] = best["lambda0"]
     res["speedup_sweeps"] = res["zero"]["sweeps_mean"] / max(best["sweeps_mean"], 1.0)
+    res["default_start"] = "network" if res["speedup_sweeps"] > 1.0 else "zero"
     net.close()
     return res

@@ -261,3 +261,26 @@ def test_warm_start_pipeline(gpu_lib):
     s0, _ = warmstart.solve_set(tep, te, sched)
     s1, _ = warmstart.solve_set(tep, te, sched, s_init=torch.zeros_like(te.d) + 1.0)
     assert float(warmstart.rel_error(s1, s0).max()) < 1e-6
+
+
+def test_warm_start_float32_targets_on_held_out_maps(gpu_lib):
+    """The configuration the benchmark runs, scaled down: float32 training
+    targets, float64 evaluation, one warm lambda0.  The sweeps ratio is taken
+    over the held-out maps only (disjoint seeds), map by map."""
+    import synth
+    from paper_1704_00865_amd import warmstart
+    trp = [synth.make_problem(64, 64, 500 + i, mask_frac=0.1) for i in range(32)]
+    tep = [synth.make_problem(64, 64, 600 + i, mask_frac=0.1) for i in range(4)]
+    print("warm start, float32 targets", flush=True)
+    res = warmstart.experiment(trp, tep, epochs=2, batch=8, lr=2e-3, warm_lam0=(1e3,),
+                               target_precision="f32", target_rtol=1e-4, target_lam0=1e4,
+                               target_shrink=0.9)
+    assert res["target_dtype"] == "f32" and res["dtype"] == "f64"
+    assert res["maps_train"] == 32 and res["maps_test"] == 4
+    assert res["held_out"] == {"train_seeds": [500, 531], "test_seeds": [600, 603],
+                               "shared_seeds": 0}
+    assert res["zero"]["converged"] == 4 and res["warm"][0]["converged"] == 4
+    assert res["warm"][0]["sweeps_ratio_per_map_median"] > 0
+    assert res["speedup_sweeps"] == pytest.approx(
+        res["zero"]["sweeps_mean"] / res["warm"][0]["sweeps_mean"])
+    assert 0 < res["target_sweeps_mean"] < 200000
