@@ -52,11 +52,18 @@ struct KP {
   static constexpr int value = ((N / 2 + 1 + TC - 1) / TC) * TC;
 };
 
+// 1/x: the hardware reciprocal (within 1 ulp) in float32, where an IEEE
+// division costs about ten instructions and the sweep's updates are about a
+// quarter of the column kernel's arithmetic; a correctly rounded division in
+// float64
+__device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ double rcp(double x) { return 1.0 / x; }
+
 template <class T>
 __device__ __forceinline__ T white_update(T d, T nb, T d1, T lt) {
   // masked pixel (Nbar = inf, stored as a negative sentinel): t_2 = d_1
   if (nb < (T)0) return d1;
-  return d1 + (lt / (nb + lt)) * (d - d1);
+  return d1 + (lt * rcp(nb + lt)) * (d - d1);
 }
 
 // The joint objective J_lambda (eqn 2mess_prob, the quadratic form that the
@@ -596,14 +603,14 @@ __device__ __forceinline__ cx<T> chain_mode(WF_GLOBAL cx<T>* tA, WF_GLOBAL cx<T>
   if constexpr (FK == FK_NONE) {
     if (k.store_first) stc(tA + idx, t2);
     if constexpr (JV) jacc += jw * cnorm2(t2) / ((double)s + k.jTW);
-    return cscale(t2, s / (s + k.TW));
+    return cscale(t2, s * rcp(s + k.TW));
   } else if constexpr (FK == FK_ARRAY_STRIPE) {
     const T nbB = (kx == 0 ? k.nxr * pst : (T)0) + k.cB;
-    const cx<T> dBn = wavg(nbB, t2, k.TW, tBo, (T)1 / (nbB + k.TW));
-    const cx<T> tBn = wavg(k.TB, dBn, nbB, dAo, (T)1 / (nbB + k.TB));
-    const cx<T> dAn = wavg(nbA, tBn, k.TB, tAo, (T)1 / (nbA + k.TB));
-    const cx<T> so = cscale(tAo, s / (s + k.SA));
-    const cx<T> tAn = wavg(k.TA, dAn, nbA, so, (T)1 / (nbA + k.TA));
+    const cx<T> dBn = wavg(nbB, t2, k.TW, tBo, rcp(nbB + k.TW));
+    const cx<T> tBn = wavg(k.TB, dBn, nbB, dAo, rcp(nbB + k.TB));
+    const cx<T> dAn = wavg(nbA, tBn, k.TB, tAo, rcp(nbA + k.TB));
+    const cx<T> so = cscale(tAo, s * rcp(s + k.SA));
+    const cx<T> tAn = wavg(k.TA, dAn, nbA, so, rcp(nbA + k.TA));
     stc(tB + idx, tBn);
     stc(dA + idx, dAn);
     stc(tA + idx, tAn);
@@ -617,9 +624,9 @@ __device__ __forceinline__ cx<T> chain_mode(WF_GLOBAL cx<T>* tA, WF_GLOBAL cx<T>
     T nb;
     if constexpr (FK == FK_ARRAY) nb = nbA;
     else nb = (kx == 0 ? k.nxr * pst : (T)0) + k.cB;
-    const cx<T> dAn = wavg(nb, t2, k.TW, tAo, (T)1 / (nb + k.TW));
-    const cx<T> so = cscale(tAo, s / (s + k.SA));
-    const cx<T> tAn = wavg(k.TA, dAn, nb, so, (T)1 / (nb + k.TA));
+    const cx<T> dAn = wavg(nb, t2, k.TW, tAo, rcp(nb + k.TW));
+    const cx<T> so = cscale(tAo, s * rcp(s + k.SA));
+    const cx<T> tAn = wavg(k.TA, dAn, nb, so, rcp(nb + k.TA));
     stc(tA + idx, tAn);
     if constexpr (JV)
       jacc += jw * (cnorm2(tAn) / ((double)s + k.jTA) + cdist2(dAn, tAn) / (double)nb +
@@ -910,7 +917,7 @@ __global__ __launch_bounds__(TC * (NY / col_elems<T, NY>()), (col_min_waves<T, N
         if (a.fk == FK_NONE) {
           if (!a.warm_chain) {
             const T s = gsc[idx];
-            v = cscale(v, s / (s + TW0));
+            v = cscale(v, s * rcp(s + TW0));
           }
         } else {
           stc(tA + idx, v);
