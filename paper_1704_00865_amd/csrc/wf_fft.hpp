@@ -216,23 +216,36 @@ struct elems {
 };
 
 // Index map of one transform's LDS exchange buffer (N complex values, E per
-// thread).  With 8-byte values and at least one wave per transform, the low
-// five bits of the index are XORed with those of 5 (j >> 5): each aligned run
-// of 32 values is permuted within itself, so natural-order accesses stay free
-// of bank conflicts, while the strided stores of the passes spread over the
-// 64 banks.  Buffers of one block are then N + 16 values apart (32 banks), so
-// a wave that touches two of them does not collide with itself.  Otherwise
-// (16-byte values, or several transforms per wave) one pad value per 16, and
-// buffers N + N/16 + 8 values apart, so that neighbouring buffers start on
-// different banks.
+// thread, NT = N/E threads).  With 8-byte values and at least one wave per
+// transform, the low five bits of the index are XORed with those of
+// 5 (j >> 5): each aligned run of 32 values is permuted within itself, so
+// natural-order accesses stay free of bank conflicts, while the strided stores
+// of the passes spread over the 64 banks.  When NT is a multiple of 256 only
+// bits 5-7 enter the XOR (as few conflicts in the passes of those plans), so
+// that element t + NT q of thread t (t < NT) sits at at(t) + NT q: the natural
+// order accesses of a thread need one address computation instead of E.
+// Buffers of one block are N + 16 values apart (32 banks), so a wave that
+// touches two of them does not collide with itself.  Otherwise (16-byte
+// values, or several transforms per wave) one pad value per 16, and buffers
+// N + N/16 + 8 values apart, so that neighbouring buffers start on different
+// banks; at(t + NT q) = at(t) + q (NT + NT/16) there when 16 divides NT.
 template <class T, int N, int E>
 struct ldsmap {
-  static constexpr bool swz = sizeof(T) == 4 && N / E >= 64;
+  static constexpr int NT = N / E;
+  static constexpr bool swz = sizeof(T) == 4 && NT >= 64;
+  static constexpr bool swz3 = swz && NT % 256 == 0;
   static_assert(!swz || N % 32 == 0, "the swizzle permutes aligned runs of 32");
   static constexpr int size = swz ? N + 16 : N + N / 16 + 8;
   __device__ __forceinline__ static int at(int j) {
-    if constexpr (swz) return j ^ ((5 * (j >> 5)) & 31);
+    if constexpr (swz3) return j ^ ((5 * ((j >> 5) & 7)) & 31);
+    else if constexpr (swz) return j ^ ((5 * (j >> 5)) & 31);
     else return j + (j >> 4);
+  }
+  // at(t + NT q) for 0 <= t < NT
+  __device__ __forceinline__ static int at_tq(int t, int q) {
+    if constexpr (swz3) return at(t) + NT * q;
+    else if constexpr (!swz && NT % 16 == 0) return at(t) + q * (NT + NT / 16);
+    else return at(t + NT * q);
   }
 };
 
@@ -376,7 +389,7 @@ __device__ __forceinline__ void stockham_pass(cx<T>* reg, cx<T>* lds, int t, TW 
   if constexpr (!LAST) {
     __syncthreads();
 #pragma unroll
-    for (int q = 0; q < E; ++q) reg[q] = lds[LM::at(t + NT * q)];
+    for (int q = 0; q < E; ++q) reg[q] = lds[LM::at_tq(t, q)];
     __syncthreads();
   }
 }

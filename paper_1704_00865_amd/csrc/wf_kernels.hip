@@ -528,7 +528,7 @@ __global__ __launch_bounds__((RW / 2) * (NX / row_elems<T, NX>()), (min_waves<T,
   if constexpr (LTW) fft<T, NX, false, E, true>(reg, lds + p * XS, t, (const cx<T>*)twl);
   else fft<T, NX, false, E, false>(reg, lds + p * XS, t, twg);
 #pragma unroll
-  for (int q = 0; q < E; ++q) lds[p * XS + LM::at(t + NT * q)] = reg[q];
+  for (int q = 0; q < E; ++q) lds[p * XS + LM::at_tq(t, q)] = reg[q];
   __syncthreads();
   if constexpr (JV) {
     if (jdo && tid == 0) gmem(a.jpart)[blk] = sum_partials(jsh, blockDim.x);
@@ -764,7 +764,7 @@ __global__ __launch_bounds__(TC * (NY / col_elems<T, NY>()), (col_min_waves<T, N
     if constexpr (LTW) tws.store(twl, tid);
     __syncthreads();
 #pragma unroll
-    for (int q = 0; q < E; ++q) reg[q] = lds[c * YS + LM::at(t + NT * q)];
+    for (int q = 0; q < E; ++q) reg[q] = lds[c * YS + LM::at_tq(t, q)];
     __syncthreads();
     if constexpr (LTW) fft<T, NY, false, E, true>(reg, lds + c * YS, t, (const cx<T>*)twl);
     else fft<T, NY, false, E, false>(reg, lds + c * YS, t, twg);
@@ -778,7 +778,7 @@ __global__ __launch_bounds__(TC * (NY / col_elems<T, NY>()), (col_min_waves<T, N
     if (g == 0) {
       if (packed) {
 #pragma unroll
-        for (int q = 0; q < E; ++q) lds[LM::at(t + NT * q)] = reg[q];
+        for (int q = 0; q < E; ++q) lds[LM::at_tq(t, q)] = reg[q];
       }
       __syncthreads();
       cx<T> cnv[E];
@@ -794,7 +794,7 @@ __global__ __launch_bounds__(TC * (NY / col_elems<T, NY>()), (col_min_waves<T, N
       __syncthreads();
       if (packed) {
 #pragma unroll
-        for (int q = 0; q < E; ++q) cnl[LM::at(t + NT * q)] = cnv[q];
+        for (int q = 0; q < E; ++q) cnl[LM::at_tq(t, q)] = cnv[q];
       }
     }
   }
@@ -804,7 +804,7 @@ __global__ __launch_bounds__(TC * (NY / col_elems<T, NY>()), (col_min_waves<T, N
     for (int q = 0; q < E; ++q) {
       const size_t row = (size_t)(t + NT * q) * nh;
       spec[row + kxc] = reg[q];
-      if (packed) spec[row + kxn] = cnl[LM::at(t + NT * q)];
+      if (packed) spec[row + kxn] = cnl[LM::at_tq(t, q)];
     }
     return;
   }
@@ -858,7 +858,7 @@ __global__ __launch_bounds__(TC * (NY / col_elems<T, NY>()), (col_min_waves<T, N
         for (int q = 0; q <= EH; ++q) {
           if (q == EH && t != 0) break;  // k_y = NY/2 on thread 0 only
           const int ky = t + NT * q;
-          const int li = LM::at(ky);
+          const int li = LM::at_tq(t, q);
           const T ps = needP ? gps[ky] : (T)0;
           const size_t i0 = (size_t)ky, iN = (size_t)kxn * NY + ky;
           // k_y and NY - k_y of a real column are one conjugate pair; the
@@ -884,9 +884,9 @@ __global__ __launch_bounds__(TC * (NY / col_elems<T, NY>()), (col_min_waves<T, N
           cx<T> c0, cn;
           if (ky <= NY / 2) {
             c0 = reg[q];
-            cn = cnl[LM::at(ky)];
+            cn = cnl[LM::at_tq(t, q)];
           } else {
-            c0 = cconj(cnl[LM::at(ky)]);
+            c0 = cconj(cnl[LM::at_tq(t, q)]);
             cn = cconj(cnl[LM::at(NY - ky)]);
           }
           reg[q] = cx<T>{c0.re - cn.im, c0.im + cn.re};
@@ -913,7 +913,7 @@ __global__ __launch_bounds__(TC * (NY / col_elems<T, NY>()), (col_min_waves<T, N
         if (h == 1 && !packed) break;
         const int kx = h == 0 ? kxc : kxn;
         const size_t idx = (size_t)kx * NY + ky;
-        cx<T> v = h == 0 ? reg[q] : cnl[LM::at(ky)];
+        cx<T> v = h == 0 ? reg[q] : cnl[LM::at_tq(t, q)];
         if (a.fk == FK_NONE) {
           if (!a.warm_chain) {
             const T s = gsc[idx];
@@ -945,7 +945,7 @@ __global__ __launch_bounds__(TC * (NY / col_elems<T, NY>()), (col_min_waves<T, N
   if constexpr (LTW) fft<T, NY, true, E, true>(reg, lds + c * YS, t, (const cx<T>*)twl);
   else fft<T, NY, true, E, false>(reg, lds + c * YS, t, twg);
 #pragma unroll
-  for (int q = 0; q < E; ++q) lds[c * YS + LM::at(t + NT * q)] = reg[q];
+  for (int q = 0; q < E; ++q) lds[c * YS + LM::at_tq(t, q)] = reg[q];
   __syncthreads();
   for (int e = tid * EPC; e < TC * NY; e += blockDim.x * EPC) {
     const int yb = e / TRTC, w = e - yb * TRTC;
@@ -1035,7 +1035,7 @@ __global__ __launch_bounds__(kTCM * (NY / mon_elems<NY>())) void mon_col_kernel(
     if constexpr (LTW) fft<T, NY, true, E, true>(reg, lds + c * YS, t, (const cx<T>*)twl);
     else fft<T, NY, true, E, false>(reg, lds + c * YS, t, twg);
 #pragma unroll
-    for (int q = 0; q < E; ++q) lds[c * YS + LM::at(t + NT * q)] = reg[q];
+    for (int q = 0; q < E; ++q) lds[c * YS + LM::at_tq(t, q)] = reg[q];
     __syncthreads();
     for (int e = tid; e < kTCM * NY; e += blockDim.x) {
       const int yb = e / TRTC, w = e - yb * TRTC;
