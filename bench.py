@@ -98,7 +98,7 @@ def _args():
     ap.add_argument("--ttr-paths", default="all",
                     help="comma-separated time-to-1e-6 entries to run (default all): "
                          "f64_shrink0.97, f64_shrink0.9, f64_paper_recipe, f32_refined, "
-                         "f64_stop_full")
+                         "f32_refined_k16, f64_stop_full")
     ap.add_argument("--warm-size", type=int, default=1024)
     ap.add_argument("--warm-train", type=int, default=2000)
     ap.add_argument("--warm-test", type=int, default=200)
@@ -238,8 +238,9 @@ def bench_time_to_rtol(wf, torch, dev, p, n, mask, tile32, paths=None):
     float64 throughout: adaptive cooling from 1e4 with lambda <- lambda^0.97
     and ^0.9 on each plateau, and the paper's recipe (from 1e6, ^0.7);
     float32 sweeps with float64-residual refinement: a first solve cooled by
-    ^0.9 until lambda = 1, then corrections (from lambda 30, ^0.9) of the
-    float64 residual, each to a tenth of its right-hand side; a float64 run
+    ^0.8 with the residual checked every 8 sweeps, then corrections (from
+    lambda 300, ^0.8) of the float64 residual, each to a tenth of its
+    right-hand side (and the same with ^0.9, from 30, every 16); a float64 run
     whose stop test also takes the masked part (hypot(rho, rho_mask) <= 1e-6)
     within a bounded budget.  Each timed with kernel profiling on; the
     roofline is the mean row plus column kernel time against their
@@ -284,12 +285,11 @@ def bench_time_to_rtol(wf, torch, dev, p, n, mask, tile32, paths=None):
         torch.cuda.synchronize()
         entry(name, r2, time.perf_counter() - t1, 8, dtype="f64", lambda0=lam0, shrink=shrink,
               plateau=1e-2, monitor_every=16)
-    first = wf.Schedule(lambda0=1.0e4, shrink=0.9, rtol=1e-4, max_sweeps=30000, monitor_every=16,
-                        chain="augmented")
-    corr = wf.Schedule(lambda0=30.0, shrink=0.9, rtol=0.1, max_sweeps=30000, monitor_every=16,
-                       chain="augmented")
-    if want("f32_refined"):
-        bench_refined(wf, torch, ctx32, ctx64, args64, out64, first, corr, entry)
+    # float32 refined: (name, first solve (lambda0, shrink, rtol), correction, monitor_every)
+    for name, fs, cs, K in (("f32_refined", (1.0e4, 0.8, 1e-3), (300.0, 0.8, 0.1), 8),
+                            ("f32_refined_k16", (1.0e4, 0.9, 1e-4), (30.0, 0.9, 0.1), 16)):
+        if want(name):
+            bench_refined(wf, torch, ctx32, ctx64, args64, out64, name, fs, cs, K, entry)
     if want("f64_stop_full"):
         bench_stop_full(wf, torch, ctx64, args64, out64, entry)
     ok = {k: v for k, v in out.items() if v["status"] == "OK" and k != "f64_stop_full"}
@@ -302,8 +302,14 @@ def bench_time_to_rtol(wf, torch, dev, p, n, mask, tile32, paths=None):
     return out
 
 
-def bench_refined(wf, torch, ctx32, ctx64, args64, out64, first, corr, entry):
-    """float32 sweeps refined by float64 residuals (wf_solve_refined)."""
+def bench_refined(wf, torch, ctx32, ctx64, args64, out64, name, fs, cs, K, entry):
+    """float32 sweeps refined by float64 residuals (wf_solve_refined): a
+    first solve with schedule fs = (lambda0, shrink, rtol), then corrections
+    with cs, the residual checked every K sweeps."""
+    first = wf.Schedule(lambda0=fs[0], shrink=fs[1], rtol=fs[2], max_sweeps=30000,
+                        monitor_every=K, chain="augmented")
+    corr = wf.Schedule(lambda0=cs[0], shrink=cs[1], rtol=cs[2], max_sweeps=30000,
+                       monitor_every=K, chain="augmented")
     wf.solve_refined(ctx32, ctx64, *args64, first=first, corr=corr, max_rounds=4, rtol=1e-6,
                      out=out64)
     torch.cuda.synchronize()
@@ -311,11 +317,11 @@ def bench_refined(wf, torch, ctx32, ctx64, args64, out64, first, corr, entry):
     _, r3, tr3 = wf.solve_refined(ctx32, ctx64, *args64, first=first, corr=corr, max_rounds=4,
                                   rtol=1e-6, out=out64)
     torch.cuda.synchronize()
-    entry("f32_refined", r3, time.perf_counter() - t1, 4, dtype="f32 sweeps, f64 residual",
+    entry(name, r3, time.perf_counter() - t1, 4, dtype="f32 sweeps, f64 residual",
           rounds=r3["refine_rounds"],
           per_round=[{"sweeps_so_far": int(t[1]), "rho": t[2]} for t in tr3],
-          first={"lambda0": 1e4, "shrink": 0.9, "rtol": 1e-4},
-          correction={"lambda0": 30.0, "shrink": 0.9, "rtol": 0.1}, monitor_every=16)
+          first={"lambda0": fs[0], "shrink": fs[1], "rtol": fs[2]},
+          correction={"lambda0": cs[0], "shrink": cs[1], "rtol": cs[2]}, monitor_every=K)
 
 
 def bench_stop_full(wf, torch, ctx64, args64, out64, entry):

@@ -204,10 +204,13 @@ size_t wf_noalloc_scratch_bytes(void);
  *                 and WF_F64;
  *   in            float64 DEVICE inputs (as for ctx64); float32 copies are
  *                 made on ctx32 (allocated on its first refined solve);
- *   first, corr   schedules of round 0 and of the corrections (field_mode
- *                 0; their rtol applies to each float32 solve, relative to
- *                 its own right-hand side);
- *   s_out         float64 DEVICE [ny*nx], s = S x;
+ *   first, corr   schedules of round 0 and of the corrections (their rtol
+ *                 applies to each float32 solve, relative to its own
+ *                 right-hand side); corr->field_mode must be 0, and
+ *                 first->field_mode 1 selects the output below;
+ *   s_out         float64 DEVICE [ny*nx], s = S x, or with first->field_mode
+ *                 1 the chain field u = S_chain x (as wf_solve's output in
+ *                 that mode);
  *   rep           rho and rho_mask of the final float64 residual, total
  *                 sweeps, refine_rounds (= n_records), the float32 solves'
  *                 kernel timing when ctx32 profiles; status WF_OK when

@@ -928,7 +928,8 @@ wf_status solve_batch_t(Ctx** ctxs, int n, const wf_inputs* ins, const wf_schedu
 //   sweeps; x_acc += x of that solve.
 // The filter is linear and (I + N S^-1) is its inverse on the observed
 // pixels (Section 2), so each correction removes the residual of x_acc up
-// to the float32 solve's own relative accuracy.  Output s = S x_acc.
+// to the float32 solve's own relative accuracy.  Output s = S x_acc, or the
+// chain field u = S_chain x_acc when the first schedule asks for field mode 1.
 wf_status ensure(void** p, size_t bytes) {
   return *p ? WF_OK : alloc(p, bytes);
 }
@@ -977,6 +978,7 @@ wf_status solve_refined(Ctx* c32, Ctx* c64, const wf_inputs* in, const wf_schedu
     mh[i].rout = (float*)c32->ref_d;
   }
   mh[1].s_out = s_out;
+  mh[1].out_chain = first->field_mode;  // 1: u = S_chain x instead of s = S x
   const MonArgs<double>* dm = (const MonArgs<double>*)c64->ref_margs;
   WF_TRY(hipMemcpyAsync(c64->ref_margs, mh, sizeof(mh), hipMemcpyHostToDevice, st));
   WF_TRY(hipStreamSynchronize(st));  // mh is this frame's memory
@@ -1242,7 +1244,7 @@ wf_status wf_solve_refined(void* ctx32, void* ctx64, const wf_inputs* in,
   wf_status v = check_schedule(first);
   if (v == WF_OK) v = check_schedule(corr);
   if (v != WF_OK) return v;
-  if (first->field_mode != 0 || corr->field_mode != 0) return WF_EINVAL;
+  if (corr->field_mode != 0) return WF_EINVAL;  // first: 0 or 1 (check_schedule)
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess || dev != c32->device) return WF_EINVAL;
   return solve_refined(c32, c64, in, first, corr, max_rounds, rtol, s_out, rep, trace, stream);

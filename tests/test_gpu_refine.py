@@ -72,3 +72,65 @@ def test_refined_reports_not_converged_when_rounds_run_out(gpu_lib):
     s, rep = _refine(gpu_lib, p, 1e-14, rounds=0)
     assert rep["status"] == "NOT_CONVERGED" and rep["refine_rounds"] == 1
     assert np.all(np.isfinite(s))
+
+
+def test_refined_c3_residual_checked_by_oracle(gpu_lib):
+    """The benchmark's fastest route to rho <= 1e-6 on the masked 2048^2 map
+    (float32 sweeps cooled by lambda^0.8 with checks every 8 sweeps, float64
+    refinement): the oracle evaluates Section 2's residual of the returned
+    chain field u = S_chain x itself and finds rho <= 1e-6, equal to the
+    library's own float64 figure."""
+    import torch
+    import oracle
+    p = synth.named_config("c3")
+    n = p.d.shape[0]
+    print("refined c3, oracle residual", flush=True)
+    c32 = gpu_lib.Context(n, n, "f32")
+    c64 = gpu_lib.Context(n, n, "f64")
+    first = gpu_lib.Schedule(lambda0=1e4, shrink=0.8, rtol=1e-3, max_sweeps=30000,
+                             monitor_every=8, chain="augmented", chain_field=True)
+    corr = gpu_lib.Schedule(lambda0=300.0, shrink=0.8, rtol=0.1, max_sweeps=30000,
+                            monitor_every=8, chain="augmented")
+    mask = torch.tensor(p.mask, dtype=torch.uint8, device="cuda")
+    u, rep, trace = gpu_lib.solve_refined(c32, c64, _t(p.d, torch), _t(p.s_k, torch),
+                                          _t(p.n_pix, torch), _t(p.p_oof, torch),
+                                          _t(p.p_stripe, torch), mask, first=first, corr=corr,
+                                          max_rounds=4, rtol=1e-6)
+    print(f"  {rep['status']} rounds {rep['refine_rounds']} sweeps {rep['sweeps']} "
+          f"rho {rep['rho']:.2e} rho_mask {rep['rho_mask']:.2e}", flush=True)
+    assert rep["status"] == "OK"
+    st = oracle.setup(p, oracle.Settings(chain="augmented"))
+    dg = oracle.diagnostics_of_field(st, u.cpu().numpy())
+    print(f"  oracle: rho {dg.rho:.3e} rho_mask {dg.rho_mask:.3e}", flush=True)
+    assert dg.rho <= 1e-6
+    assert dg.rho == pytest.approx(rep["rho"], rel=1e-6)
+    assert dg.rho_mask == pytest.approx(rep["rho_mask"], rel=1e-6)
+
+
+def test_refined_output_modes_agree(gpu_lib):
+    """s = S x and u = S_chain x from the same refined solve: u's signal part
+    S (S + N_F)^-1 u equals s (64^2, three terms, mask)."""
+    import torch
+    p = synth.make_problem(64, 64, 7, mask_frac=0.1)
+    outs = []
+    for cf in (False, True):
+        c32 = gpu_lib.Context(64, 64, "f32")
+        c64 = gpu_lib.Context(64, 64, "f64")
+        first = gpu_lib.Schedule(lambda0=1e4, shrink=0.9, rtol=1e-4, max_sweeps=20000,
+                                 monitor_every=8, chain="augmented", chain_field=cf)
+        corr = gpu_lib.Schedule(lambda0=100.0, shrink=0.9, rtol=0.05, max_sweeps=20000,
+                                monitor_every=8, chain="augmented")
+        mask = torch.tensor(p.mask, dtype=torch.uint8, device="cuda")
+        s, rep, _ = gpu_lib.solve_refined(c32, c64, _t(p.d, torch), _t(p.s_k, torch),
+                                          _t(p.n_pix, torch), _t(p.p_oof, torch),
+                                          _t(p.p_stripe, torch), mask, first=first, corr=corr,
+                                          max_rounds=3, rtol=1e-9)
+        outs.append((s.cpu().numpy(), rep))
+    (s, r0), (u, r1) = outs
+    assert r0["rho"] == r1["rho"] and r0["sweeps"] == r1["sweeps"]
+    # s = S S_chain^-1 u, mode by mode (unitary transforms of the oracle)
+    import oracle
+    from oracle.bases import irfft2u, rfft2u
+    st = oracle.setup(p, oracle.Settings(chain="augmented"))
+    s_from_u = irfft2u(rfft2u(u) * (st.S.eig / st.S_chain.eig), u.shape)
+    assert np.linalg.norm(s_from_u - s) / np.linalg.norm(s) < 1e-12
