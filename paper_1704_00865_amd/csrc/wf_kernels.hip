@@ -1097,6 +1097,25 @@ __global__ __launch_bounds__(kRWM * (NX / mon_elems<NX>())) void mon_row_kernel(
   }
   TwiddleStage<T, NX, E, NTHR> tws;
   if constexpr (LTW) tws.load(twg, tid);
+  // the residual's inputs for this thread's pixels, loaded with the bands
+  // (before the transform; 56 -> 51 us per check at 2048^2: this kernel has
+  // the registers and the band is not delayed, unlike in the sweep's row
+  // kernel, where the same prefetch made it slower)
+  const int r = tid / NT, t = tid - r * NT;
+  const int y = y0 + r;
+  const WF_GLOBAL T* mn2 = gmem(m.nbar2);
+  const WF_GLOBAL T* mnp = gmem(m.npix);
+  const WF_GLOBAL T* md = gmem(m.d);
+  T pn2[E], pnp[E], pdd[E];
+  if (mode != MON_OUTPUT) {
+#pragma unroll
+    for (int q = 0; q < E; ++q) {
+      const size_t i = (size_t)y * NX + t + NT * q;
+      pn2[q] = mn2[i];
+      pnp[q] = mnp[i];
+      pdd[q] = md[i];
+    }
+  }
 #pragma unroll
   for (int i = 0; i < NB; ++i) {
     const int e = tid + i * NTHR;
@@ -1109,7 +1128,6 @@ __global__ __launch_bounds__(kRWM * (NX / mon_elems<NX>())) void mon_row_kernel(
   }
   if constexpr (LTW) tws.store(twl, tid);
   __syncthreads();
-  const int r = tid / NT, t = tid - r * NT;
   cx<T> reg[E];
 #pragma unroll
   for (int q = 0; q < E; ++q) {
@@ -1131,10 +1149,6 @@ __global__ __launch_bounds__(kRWM * (NX / mon_elems<NX>())) void mon_row_kernel(
   __syncthreads();
   if constexpr (LTW) fft<T, NX, true, E, true>(reg, lds + r * XS, t, (const cx<T>*)twl);
   else fft<T, NX, true, E, false>(reg, lds + r * XS, t, twg);
-  const WF_GLOBAL T* mn2 = gmem(m.nbar2);
-  const WF_GLOBAL T* mnp = gmem(m.npix);
-  const WF_GLOBAL T* md = gmem(m.d);
-  const int y = y0 + r;
   double a_dd = 0.0, a_mx = 0.0;
 #pragma unroll
   for (int q = 0; q < E; ++q) {
@@ -1142,8 +1156,8 @@ __global__ __launch_bounds__(kRWM * (NX / mon_elems<NX>())) void mon_row_kernel(
     const double xv = (double)reg[q].re * m.scale, yv = (double)reg[q].im * m.scale;
     if (mode == MON_OUTPUT) {
       s_out[i] = (T)yv;
-    } else if (mn2[i] >= (T)0) {
-      const double dd = yv + (double)mnp[i] * xv - (double)md[i];
+    } else if (pn2[q] >= (T)0) {
+      const double dd = yv + (double)pnp[q] * xv - (double)pdd[q];
       a_dd += dd * dd;
       if (mode == MON_REFINE) gmem(m.rout)[i] = (float)(-dd);
     } else {
