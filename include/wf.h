@@ -207,7 +207,10 @@ size_t wf_noalloc_scratch_bytes(void);
  *   first, corr   schedules of round 0 and of the corrections (their rtol
  *                 applies to each float32 solve, relative to its own
  *                 right-hand side); corr->field_mode must be 0, and
- *                 first->field_mode 1 selects the output below;
+ *                 first->field_mode selects what s_init and s_out are;
+ *   s_init        float64 DEVICE [ny*nx] warm start of round 0 (the signal s,
+ *                 or with first->field_mode 1 the chain field u, as for
+ *                 wf_solve; rounded to float32 for that solve), or NULL;
  *   s_out         float64 DEVICE [ny*nx], s = S x, or with first->field_mode
  *                 1 the chain field u = S_chain x (as wf_solve's output in
  *                 that mode);
@@ -220,8 +223,8 @@ size_t wf_noalloc_scratch_bytes(void);
  * Synchronises stream. */
 wf_status wf_solve_refined(void* ctx32, void* ctx64, const wf_inputs* in,
                            const wf_schedule* first, const wf_schedule* corr, int32_t max_rounds,
-                           double rtol, void* s_out, wf_report* rep, double* trace,
-                           hipStream_t stream);
+                           double rtol, const void* s_init, void* s_out, wf_report* rep,
+                           double* trace, hipStream_t stream);
 
 /* Largest batch wf_solve_batch accepts. */
 #define WF_BATCH_MAX 1024

@@ -112,7 +112,7 @@ def load():
     lib.wf_noalloc_scratch_bytes.argtypes = []
     lib.wf_noalloc_scratch_bytes.restype = ctypes.c_size_t
     lib.wf_solve_refined.argtypes = [vp, vp, ctypes.POINTER(_Inputs), ctypes.POINTER(_Schedule),
-                                     ctypes.POINTER(_Schedule), i32, ctypes.c_double, vp,
+                                     ctypes.POINTER(_Schedule), i32, ctypes.c_double, vp, vp,
                                      ctypes.POINTER(_Report), ctypes.POINTER(ctypes.c_double), vp]
     lib.wf_solve_refined.restype = i32
     lib.wf_autotune.argtypes = [vp, ctypes.POINTER(_Inputs), i32, vp,
@@ -398,11 +398,12 @@ def solve(d, s_k, n_pix, p_oof=None, p_stripe=None, mask=None, *, schedule=Sched
 
 def solve_refined(ctx32, ctx64, d, s_k, n_pix, p_oof=None, p_stripe=None, mask=None, *,
                   first: Schedule, corr: Schedule, max_rounds: int = 4, rtol: float = 1e-6,
-                  out=None):
+                  s_init=None, out=None):
     """``wf_solve_refined``: float32 solves on ``ctx32`` refined with float64
     residuals on ``ctx64`` (same shape).  Inputs are float64 tensors as for
-    ``ctx64``.  Returns (s float64, report dict, trace array of (round,
-    sweeps so far, rho, rho_mask) after each round)."""
+    ``ctx64``; ``s_init`` (float64) warm-starts round 0 in ``first``'s field
+    mode.  Returns (s float64, report dict, trace array of (round, sweeps so
+    far, rho, rho_mask) after each round)."""
     import torch
     lib = load()
     if ctx32.dtype != torch.float32 or ctx64.dtype != torch.float64:
@@ -415,6 +416,7 @@ def solve_refined(ctx32, ctx64, d, s_k, n_pix, p_oof=None, p_stripe=None, mask=N
     ctx64._check(p_oof, (ny, nh), "p_oof")
     ctx64._check(p_stripe, (ny,), "p_stripe")
     ctx64._check(mask, (ny, nx), "mask", torch.uint8)
+    ctx64._check(s_init, (ny, nx), "s_init")
     if out is None:
         out = torch.empty((ny, nx), dtype=torch.float64, device=ctx64.device)
     ctx64._check(out, (ny, nx), "out")
@@ -426,6 +428,7 @@ def solve_refined(ctx32, ctx64, d, s_k, n_pix, p_oof=None, p_stripe=None, mask=N
     with torch.cuda.device(ctx64.device):
         st = lib.wf_solve_refined(ctx32._h, ctx64._h, ctypes.byref(inp), ctypes.byref(s1),
                                   ctypes.byref(s2), int(max_rounds), ctypes.c_double(rtol),
+                                  None if s_init is None else ctypes.c_void_p(s_init.data_ptr()),
                                   out.data_ptr(), ctypes.byref(rep),
                                   trace.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
                                   _stream_ptr(torch, ctx64.device))

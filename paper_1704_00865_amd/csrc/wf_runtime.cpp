@@ -84,6 +84,7 @@ struct Ctx {
   void* ref_poof = nullptr;
   void* ref_pst = nullptr;
   void* ref_out = nullptr;
+  void* ref_init = nullptr;  // float32 copy of a warm start of round 0
   void* ref_margs = nullptr;
   // one chunk of the single-map solve recorded as a HIP graph on cap_stream,
   // replayed for every chunk; valid for the (K, last sweep of the budget
@@ -167,7 +168,7 @@ void free_ctx(Ctx* c) {
   void* bufs[] = {c->B, c->tA, c->dA, c->tB, c->sc, c->nbA, c->sy, c->sig, c->nbar2, c->twx, c->twy,
                   c->Mx, c->My, c->part, c->jpart, c->stats, c->sch, c->lam, c->trace,
                   c->alpha_sk, c->d_args, c->d_margs, c->d_ctrl, c->ref_d, c->ref_npix,
-                  c->ref_sk, c->ref_poof, c->ref_pst, c->ref_out, c->ref_margs};
+                  c->ref_sk, c->ref_poof, c->ref_pst, c->ref_out, c->ref_init, c->ref_margs};
   for (void* p : bufs)
     if (p) (void)hipFree(p);
   if (c->h_ring) (void)hipHostFree(c->h_ring);
@@ -922,7 +923,8 @@ wf_status solve_batch_t(Ctx** ctxs, int n, const wf_inputs* ins, const wf_schedu
 //
 // x = S^-1 s is accumulated in float64 (state layout [kx][ky], unnormalised
 // like every Fourier field here) on the float64 context:
-//   round 0: solve the data with float32 sweeps; x_acc = x of that solve;
+//   round 0: solve the data with float32 sweeps (from a warm start if one
+//   is given); x_acc = x of that solve;
 //   then, while rho > rtol: evaluate Delta d = d_rec(x_acc) - d in float64
 //   and solve -Delta d (observed pixels; 0 on masked ones) with float32
 //   sweeps; x_acc += x of that solve.
@@ -935,8 +937,8 @@ wf_status ensure(void** p, size_t bytes) {
 }
 
 wf_status solve_refined(Ctx* c32, Ctx* c64, const wf_inputs* in, const wf_schedule* first,
-                        const wf_schedule* corr, int max_rounds, double rtol, void* s_out,
-                        wf_report* rep, double* trace, hipStream_t st) {
+                        const wf_schedule* corr, int max_rounds, double rtol, const void* s_init,
+                        void* s_out, wf_report* rep, double* trace, hipStream_t st) {
   const size_t ny = c32->ny, nx = c32->nx, nh = c32->nh;
   const size_t npix = ny * nx, modes = ny * nh;
   wf_status e;
@@ -944,6 +946,7 @@ wf_status solve_refined(Ctx* c32, Ctx* c64, const wf_inputs* in, const wf_schedu
   if ((e = ensure(&c32->ref_npix, npix * 4)) != WF_OK) return e;
   if ((e = ensure(&c32->ref_sk, modes * 4)) != WF_OK) return e;
   if ((e = ensure(&c32->ref_out, npix * 4)) != WF_OK) return e;
+  if (s_init && (e = ensure(&c32->ref_init, npix * 4)) != WF_OK) return e;
   if (in->p_oof && (e = ensure(&c32->ref_poof, modes * 4)) != WF_OK) return e;
   if (in->p_stripe && (e = ensure(&c32->ref_pst, ny * 4)) != WF_OK) return e;
   if ((e = ensure(&c64->ref_margs, 2 * sizeof(MonArgs<double>))) != WF_OK) return e;
@@ -960,6 +963,8 @@ wf_status solve_refined(Ctx* c32, Ctx* c64, const wf_inputs* in, const wf_schedu
     WF_TRY(launch_to_float((const double*)in->p_oof, (int64_t)modes, (float*)c32->ref_poof, st));
   if (in->p_stripe)
     WF_TRY(launch_to_float((const double*)in->p_stripe, (int64_t)ny, (float*)c32->ref_pst, st));
+  if (s_init)
+    WF_TRY(launch_to_float((const double*)s_init, (int64_t)npix, (float*)c32->ref_init, st));
   wf_inputs in32 = *in;
   in32.d = c32->ref_d;
   in32.n_pix = c32->ref_npix;
@@ -990,7 +995,8 @@ wf_status solve_refined(Ctx* c32, Ctx* c64, const wf_inputs* in, const wf_schedu
   for (int j = 0; j <= max_rounds; ++j) {
     wf_report rj;
     Chain chj;
-    const wf_status sj = solve_t<float>(c32, &in32, j == 0 ? first : corr, nullptr, c32->ref_out,
+    const void* init = (j == 0 && s_init) ? c32->ref_init : nullptr;
+    const wf_status sj = solve_t<float>(c32, &in32, j == 0 ? first : corr, init, c32->ref_out,
                                         &rj, nullptr, st, &chj);
     if (sj < 0) return sj;
     last_status = sj;
@@ -1232,8 +1238,8 @@ size_t wf_noalloc_scratch_bytes(void) { return kStaticBytes; }
 
 wf_status wf_solve_refined(void* ctx32, void* ctx64, const wf_inputs* in,
                            const wf_schedule* first, const wf_schedule* corr, int32_t max_rounds,
-                           double rtol, void* s_out, wf_report* rep, double* trace,
-                           hipStream_t stream) {
+                           double rtol, const void* s_init, void* s_out, wf_report* rep,
+                           double* trace, hipStream_t stream) {
   Ctx* c32 = (Ctx*)ctx32;
   Ctx* c64 = (Ctx*)ctx64;
   if (!c32 || !c64 || !in || !first || !corr || !s_out || !in->d || !in->s_k || !in->n_pix)
@@ -1247,7 +1253,8 @@ wf_status wf_solve_refined(void* ctx32, void* ctx64, const wf_inputs* in,
   if (corr->field_mode != 0) return WF_EINVAL;  // first: 0 or 1 (check_schedule)
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess || dev != c32->device) return WF_EINVAL;
-  return solve_refined(c32, c64, in, first, corr, max_rounds, rtol, s_out, rep, trace, stream);
+  return solve_refined(c32, c64, in, first, corr, max_rounds, rtol, s_init, s_out, rep, trace,
+                       stream);
 }
 
 wf_status wf_solve_batch(void* const* ctxs, int32_t n, const wf_inputs* inputs,

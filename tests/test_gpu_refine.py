@@ -134,3 +134,35 @@ def test_refined_output_modes_agree(gpu_lib):
     st = oracle.setup(p, oracle.Settings(chain="augmented"))
     s_from_u = irfft2u(rfft2u(u) * (st.S.eig / st.S_chain.eig), u.shape)
     assert np.linalg.norm(s_from_u - s) / np.linalg.norm(s) < 1e-12
+
+
+def test_refined_warm_start_from_the_solution_needs_one_round(gpu_lib):
+    """Round 0 warm-started (field mode 1) from the refined solution's own
+    chain field: the float32 solve starts at its fixed point, so the float64
+    residual is at the float32 rounding level after one check, and the
+    refinement from there ends where the first one did."""
+    import torch
+    p = synth.make_problem(128, 128, 8, mask_frac=0.1)
+    c32 = gpu_lib.Context(128, 128, "f32")
+    c64 = gpu_lib.Context(128, 128, "f64")
+    mask = torch.tensor(p.mask, dtype=torch.uint8, device="cuda")
+    args = (_t(p.d, torch), _t(p.s_k, torch), _t(p.n_pix, torch), _t(p.p_oof, torch),
+            _t(p.p_stripe, torch), mask)
+
+    def sched(lam0, cf):
+        return gpu_lib.Schedule(lambda0=lam0, shrink=0.8, rtol=1e-3, max_sweeps=20000,
+                                monitor_every=8, chain="augmented", chain_field=cf)
+    corr = gpu_lib.Schedule(lambda0=300.0, shrink=0.8, rtol=0.1, max_sweeps=20000,
+                            monitor_every=8, chain="augmented")
+    u, rep0, _ = gpu_lib.solve_refined(c32, c64, *args, first=sched(1e4, True), corr=corr,
+                                       max_rounds=4, rtol=1e-8)
+    assert rep0["status"] == "OK"
+    u1, rep1, tr1 = gpu_lib.solve_refined(c32, c64, *args, first=sched(1.0, True), corr=corr,
+                                          max_rounds=4, rtol=1e-8, s_init=u)
+    print(f"  from zero: {rep0['sweeps']} sweeps; from its own solution: {rep1['sweeps']} "
+          f"sweeps, rho after round 0 {tr1[0][2]:.2e}", flush=True)
+    assert rep1["status"] == "OK"
+    assert tr1[0][1] <= 16 and tr1[0][2] < 1e-4
+    assert rep1["sweeps"] < rep0["sweeps"]
+    u_np, u1_np = u.cpu().numpy(), u1.cpu().numpy()
+    assert np.linalg.norm(u1_np - u_np) / np.linalg.norm(u_np) < 1e-4
