@@ -980,6 +980,8 @@ __global__ __launch_bounds__(kTCM * (NY / mon_elems<NY>())) void mon_col_kernel(
   using LM = ldsmap<T, NY, E>;  // exchange-buffer index map
   constexpr int YS = LM::size;
   constexpr int TRTC = kTRM * kTCM;
+  constexpr int EPC = 16 / (2 * (int)sizeof(T));  // complex values per 16 bytes
+  static_assert(TRTC % EPC == 0, "16-byte runs stay within a tile");
   __shared__ __align__(16) cx<T> lds[kTCM * YS];
   constexpr bool LTW = lds_twiddles<T, NY>();
   __shared__ cx<T> twl[LTW ? NY : 1];
@@ -1037,10 +1039,16 @@ __global__ __launch_bounds__(kTCM * (NY / mon_elems<NY>())) void mon_col_kernel(
 #pragma unroll
     for (int q = 0; q < E; ++q) lds[c * YS + LM::at_tq(t, q)] = reg[q];
     __syncthreads();
-    for (int e = tid; e < kTCM * NY; e += blockDim.x) {
+    // 16-byte stores: EPC consecutive values of a tile
+    for (int e = tid * EPC; e < kTCM * NY; e += blockDim.x * EPC) {
       const int yb = e / TRTC, w = e - yb * TRTC;
-      const int r = w / kTCM, cc = w - r * kTCM;
-      stc(dst + ((size_t)yb * G + g) * TRTC + w, lds[cc * YS + LM::at(yb * kTRM + r)]);
+      cx<T> v[EPC];
+#pragma unroll
+      for (int u = 0; u < EPC; ++u) {
+        const int r = (w + u) / kTCM, cc = (w + u) - r * kTCM;
+        v[u] = lds[cc * YS + LM::at(yb * kTRM + r)];
+      }
+      copy16(dst + ((size_t)yb * G + g) * TRTC + w, v);
     }
     __syncthreads();
   }
@@ -1083,16 +1091,18 @@ __global__ __launch_bounds__(kRWM * (NX / mon_elems<NX>())) void mon_row_kernel(
   // first LDS write; value e of the band is row rr, column g kTCM + cc with
   // g = e / (kRWM kTCM): each tile holds kRWM kTCM consecutive values of it
   constexpr int NTHR = kRWM * NT;
-  constexpr int NB = (BANDm + NTHR - 1) / NTHR;
-  cx<T> bx[NB], by[NB];
+  constexpr int EPC = 16 / (2 * (int)sizeof(T));  // complex values per 16-byte load
+  static_assert(BANDm % EPC == 0 && (kRWM * kTCM) % EPC == 0, "16-byte runs stay in a tile");
+  constexpr int NB = (BANDm + NTHR * EPC - 1) / (NTHR * EPC);
+  cx<T> bx[NB][EPC], by[NB][EPC];
 #pragma unroll
   for (int i = 0; i < NB; ++i) {
-    const int e = tid + i * NTHR;
+    const int e = (tid + i * NTHR) * EPC;
     if (e < BANDm) {
       const int g = e / (kRWM * kTCM), w = e - g * (kRWM * kTCM);
       const size_t off = (size_t)g * TRTC + w;
-      bx[i] = ldc(gx + off);
-      by[i] = ldc(gy + off);
+      copy16(bx[i], gx + off);
+      copy16(by[i], gy + off);
     }
   }
   TwiddleStage<T, NX, E, NTHR> tws;
@@ -1118,12 +1128,16 @@ __global__ __launch_bounds__(kRWM * (NX / mon_elems<NX>())) void mon_row_kernel(
   }
 #pragma unroll
   for (int i = 0; i < NB; ++i) {
-    const int e = tid + i * NTHR;
+    const int e = (tid + i * NTHR) * EPC;
     if (e < BANDm) {
-      const int g = e / (kRWM * kTCM), w = e - g * (kRWM * kTCM);
-      const int rr = w / kTCM, kx = g * kTCM + (w - rr * kTCM);
-      lds[rr * RSm + kx] = bx[i];
-      lds[(kRWM + rr) * RSm + kx] = by[i];
+      const int g = e / (kRWM * kTCM), w0 = e - g * (kRWM * kTCM);
+#pragma unroll
+      for (int u = 0; u < EPC; ++u) {
+        const int w = w0 + u;
+        const int rr = w / kTCM, kx = g * kTCM + (w - rr * kTCM);
+        lds[rr * RSm + kx] = bx[i][u];
+        lds[(kRWM + rr) * RSm + kx] = by[i][u];
+      }
     }
   }
   if constexpr (LTW) tws.store(twl, tid);
