@@ -1246,14 +1246,38 @@ __global__ __launch_bounds__(256) void scale_kernel(T* __restrict__ x, int64_t n
 }
 
 #if WF_PART & 1
+// Thread t's share of a fixed-order sum over n partials: elements t, t + B,
+// t + 2B, ... (B = blockDim.x) added in that order, their loads issued U at a
+// time before the adds (a loop of load-wait-add pairs waited on memory once
+// per element).  Pairs when PAIR (two sums over interleaved values).
+template <bool PAIR>
+__device__ __forceinline__ void thread_sums(const WF_GLOBAL double* v, int n, double& a,
+                                            double& b) {
+  constexpr int U = 8;
+  const int B = blockDim.x;
+  for (int i0 = threadIdx.x; i0 < n; i0 += U * B) {
+    double x[U], y[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int i = i0 + u * B;
+      x[u] = i < n ? v[PAIR ? 2 * i : i] : 0.0;
+      y[u] = (PAIR && i < n) ? v[2 * i + 1] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      if (i0 + u * B < n) {
+        a += x[u];
+        if (PAIR) b += y[u];
+      }
+    }
+  }
+}
+
 __global__ __launch_bounds__(256) void pair_sum_kernel(const double* __restrict__ part, int nblk,
                                                        double* __restrict__ out) {
   __shared__ double sh[16];
   double a = 0.0, b = 0.0;
-  for (int i = threadIdx.x; i < nblk; i += blockDim.x) {
-    a += part[2 * i];
-    b += part[2 * i + 1];
-  }
+  thread_sums<true>(gmem(part), nblk, a, b);
   a = block_reduce<RED_SUM>(a, sh);
   b = block_reduce<RED_SUM>(b, sh);
   if (threadIdx.x == 0) {
@@ -1274,12 +1298,9 @@ __global__ __launch_bounds__(256) void controller_kernel(const CtrlArgs* __restr
   double* __restrict__ trace = ca.trace;
   __shared__ double sh[16];
   if (s->done) return;
-  double a = 0.0, b = 0.0, jv = 0.0;
-  for (int i = threadIdx.x; i < nblk; i += blockDim.x) {
-    a += part[2 * i];
-    b += part[2 * i + 1];
-  }
-  for (int i = threadIdx.x; i < ca.njblk; i += blockDim.x) jv += ca.jpart[i];
+  double a = 0.0, b = 0.0, jv = 0.0, unused = 0.0;
+  thread_sums<true>(gmem(part), nblk, a, b);
+  thread_sums<false>(gmem(ca.jpart), ca.njblk, jv, unused);
   a = block_reduce<RED_SUM>(a, sh);
   b = block_reduce<RED_SUM>(b, sh);
   jv = block_reduce<RED_SUM>(jv, sh);
