@@ -28,8 +28,11 @@
 // float64, rounded once to the path's precision and taken to pixel space by
 // inverse transforms of that precision; Delta d = y + N_white x - d
 // (Section 2) is then summed in float64 over observed pixels, and x^2 over
-// masked ones.  A one-block controller applies the cooling schedule on the
-// device.
+// masked ones.  During a solve the column transforms of x and y run at the
+// end of each chunk's last column sweep (the J variant) and only the row pass
+// is a launch of its own; the monitor's column kernel serves the output and
+// the refinement.  A one-block controller applies the cooling schedule on
+// the device.
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <stdint.h>
@@ -956,6 +959,78 @@ __global__ __launch_bounds__(TC * (NY / col_elems<T, NY>()), (col_min_waves<T, N
       v[u] = lds[cc * YS + LM::at(yb * TR + r)];
     }
     copy16(&gB[((size_t)yb * G + g) * TRTC + w], v);
+  }
+  if constexpr (JV) {
+    if (store_first) {
+      // The monitor's column pass for this block's columns, from the state
+      // this sweep left (the chunk's last): x = t_A / (S_c + lambda tau) and
+      // y = (S + N_F) x per mode in float64, rounded once, inverse column
+      // transforms, written to the monitor transit in its own tiling.  The
+      // real columns k_x = 0 and nx/2 go through one transform as
+      // x_0 + i x_nx/2 (both transforms are real).  Fields of this block
+      // that other threads stored are read after the barrier.
+      __syncthreads();
+      const double Tf = lam * (FK == FK_NONE ? a.tauW : a.tauA);
+      const WF_GLOBAL T* gsy = gmem(a.sy);
+      auto xy = [&](int kx, int ky, cx<double>& xo, cx<double>& yo) {
+        const bool mir = (kx == 0 || kx == kxn) && ky > NY / 2;
+        const size_t idx = (size_t)kx * NY + (mir ? NY - ky : ky);
+        cx<T> v = ldc(gtA + idx);
+        if (mir) v.im = -v.im;
+        if ((kx == 0 || kx == kxn) && (ky == 0 || ky == NY / 2)) v.im = (T)0;
+        const double inv = 1.0 / ((double)gsc[idx] + Tf), f = (double)gsy[idx];
+        xo = cx<double>{(double)v.re * inv, (double)v.im * inv};
+        yo = cx<double>{xo.re * f, xo.im * f};
+      };
+      cx<T> rx[E], ry[E];
+#pragma unroll
+      for (int q = 0; q < E; ++q) {
+        const int ky = t + NT * q;
+        cx<double> x0, y0;
+        xy(kxc, ky, x0, y0);
+        if (packed) {
+          cx<double> xn, yn;
+          xy(kxn, ky, xn, yn);
+          x0 = cx<double>{x0.re - xn.im, x0.im + xn.re};
+          y0 = cx<double>{y0.re - yn.im, y0.im + yn.re};
+        }
+        rx[q] = cx<T>{(T)x0.re, (T)x0.im};
+        ry[q] = cx<T>{(T)y0.re, (T)y0.im};
+      }
+      const int GM = a.kpm / kTCM;  // monitor tiles per tile row
+#pragma unroll
+      for (int field = 0; field < 2; ++field) {
+        cx<T>* reg2 = field == 0 ? rx : ry;
+        WF_GLOBAL cx<T>* dst = gmem((cx<T>*)(field == 0 ? a.Mx : a.My));
+        if constexpr (LTW) fft<T, NY, true, E, true>(reg2, lds + c * YS, t, (const cx<T>*)twl);
+        else fft<T, NY, true, E, false>(reg2, lds + c * YS, t, twg);
+#pragma unroll
+        for (int q = 0; q < E; ++q) lds[c * YS + LM::at_tq(t, q)] = reg2[q];
+        __syncthreads();
+        // element e of this block: row y = e / TC, column g TC + e % TC; EPC
+        // consecutive values share a monitor tile row (TC and kTCM even)
+        for (int e = tid * EPC; e < TC * NY; e += blockDim.x * EPC) {
+          const int y = e / TC, cc0 = e - y * TC;
+          const int kx0 = g * TC + cc0;
+          cx<T> v[EPC];
+#pragma unroll
+          for (int u = 0; u < EPC; ++u) v[u] = lds[(cc0 + u) * YS + LM::at(y)];
+          const size_t tile = ((size_t)(y / kTRM) * GM + kx0 / kTCM) * (kTRM * kTCM);
+          const size_t off = tile + (y % kTRM) * kTCM + kx0 % kTCM;
+          if (g == 0 && cc0 == 0) {
+            // block 0's column 0 holds x_0 + i x_nx/2 (whichever thread
+            // writes it): split into the two real columns
+            const cx<T> z = v[0];
+            v[0] = cx<T>{z.re, (T)0};
+            const size_t tn = ((size_t)(y / kTRM) * GM + kxn / kTCM) * (kTRM * kTCM) +
+                              (y % kTRM) * kTCM + kxn % kTCM;
+            stc(dst + tn, cx<T>{z.im, (T)0});
+          }
+          copy16(dst + off, v);
+        }
+        __syncthreads();
+      }
+    }
   }
 }
 

@@ -78,6 +78,11 @@ struct SweepArgs {
   int32_t warm_chain;     // warm start gives the chain's signal-end field itself
   int32_t jrow;           // row-kernel blocks: column partials of J start there
   double* jpart;          // per-block partial sums of the joint objective
+  // the monitor's column pass, run by the chunk's last column sweep
+  const T* sy;            // [kx][ky] factor of y = (S + N_F) x for the residual
+  void* Mx;               // monitor transit, tiled [y/kTRM][kx/kTCM][kTRM][kTCM]
+  void* My;
+  int32_t kpm;            // monitor transit columns (nx/2 + 1, padded to kTCM)
 };
 
 // per-mode coefficient preparation (see prep_spectra_kernel)

@@ -348,6 +348,10 @@ SweepArgs<T> sweep_args(Ctx* c, const wf_inputs* in, const Chain& ch) {
   a.scale = 1.0 / ((double)c->nx * (double)c->ny);
   a.jrow = c->ny / kTiles[c->tile].RW;
   a.jpart = c->jpart;
+  a.sy = (const T*)c->sy;
+  a.Mx = c->Mx;
+  a.My = c->My;
+  a.kpm = c->kpm;
   return a;
 }
 
@@ -564,9 +568,9 @@ wf_status enqueue_chunk(std::vector<ShapeClass<T>>& cls, const std::vector<MapRu
     }
   }
   if (ev) WF_TRY(hipEventRecord(ev[4], st));
+  // the monitor's column pass ran in the chunk's last column sweep
   for (auto& cl : cls) {
     const MonArgs<T>& m0 = runs[cl.maps[0]].m;
-    WF_TRY(launch_mon_col<T>(m0, cl.margv, (int)cl.maps.size(), MON_RESIDUAL, st));
     WF_TRY(launch_mon_row<T>(m0, cl.margv, (int)cl.maps.size(), MON_RESIDUAL, st));
   }
   WF_TRY(launch_controller(ctrl_argv, nmaps, st));
@@ -589,7 +593,7 @@ wf_status enqueue_class(ShapeClass<T>& cl, const std::vector<MapRun<T>>& runs, i
     WF_TRY(launch_col<T>(cl.tile, jv ? COL_SWEEP_J : COL_SWEEP, a0, cl.argv, n, k, nullptr, 0.0,
                          st));
   }
-  WF_TRY(launch_mon_col<T>(m0, cl.margv, n, MON_RESIDUAL, st));
+  // the monitor's column pass ran in the chunk's last column sweep
   WF_TRY(launch_mon_row<T>(m0, cl.margv, n, MON_RESIDUAL, st));
   return WF_OK;
 }
