@@ -283,22 +283,25 @@ def test_full_size_parity_float32_1024(gpu_lib):
     _assert_parity(s_gpu, res.s, "f32")
 
 
-@pytest.mark.parametrize("n,tile", [(1536, 1), (1536, 5), (768, 3)])
-def test_full_size_parity_float32_radix3(gpu_lib, n, tile):
-    """The float32 12-value kernels (five-pass 1536-point plan, four-pass
-    768-point plan) at the batch's full sizes, in the default tiling and in
-    the ones the batch's autotuner picks, masked C3 recipe, against the
-    oracle."""
+@pytest.mark.parametrize("prec,n,tile", [("f32", 1536, 1), ("f32", 1536, 5), ("f32", 768, 3),
+                                         ("f64", 1536, 1)])
+def test_full_size_parity_radix3(gpu_lib, prec, n, tile):
+    """The 12-value kernels (five-pass 1536-point plan, four-pass 768-point
+    plan) at the batch's full sizes, in the default tiling and in the ones
+    the batch's autotuner picks (float32), masked C3 recipe, against the
+    oracle; the residual trace too."""
     oracle.bases.set_workers(16)
     p = synth.make_problem(n, n, 3, mask_frac=0.10)
     lams = list(_ramp(40, 50, 1e4))
-    print(f"parity f32 {n}x{n} tiling {tile}", flush=True)
-    ctx = gpu_lib.Context(n, n, "f32")
+    print(f"parity {prec} {n}x{n} tiling {tile}", flush=True)
+    ctx = gpu_lib.Context(n, n, prec)
     assert ctx.set_tile(tile)
     sched = gpu_lib.Schedule(lambdas=lams, rtol=0.0, max_sweeps=len(lams), monitor_every=16)
-    s_gpu, rep, trace = ctx.solve(*_tensors(p, "f32"), schedule=sched)
+    s_gpu, rep, trace = ctx.solve(*_tensors(p, prec), schedule=sched)
     res = oracle.solve(p, oracle.FixedSchedule(lams), max_sweeps=len(lams), monitor_every=16)
-    _assert_parity(s_gpu.cpu().numpy().astype(np.float64), res.s, "f32")
+    _assert_parity(s_gpu.cpu().numpy().astype(np.float64), res.s, prec)
+    for g, o in zip(trace, res.trace):
+        assert g[2] == pytest.approx(o[2], rel=1e-8 if prec == "f64" else 2e-3)
 
 
 def test_c3_benchmark_run_parity(gpu_lib):
