@@ -379,6 +379,14 @@ template <class T, int N>
 constexpr int col_min_waves() {
   return col_elems<T, N>() == 8 ? 4 : min_waves<T, N>();
 }
+// the chunk's last sweep (joint objective and the monitor's column
+// transforms) runs once per chunk: one wave per SIMD fewer, so that its
+// longer body does not spill
+template <class T, int N, int MODE>
+constexpr int col_waves() {
+  return (MODE == COL_SWEEP_J && col_min_waves<T, N>() > 2) ? col_min_waves<T, N>() - 1
+                                                              : col_min_waves<T, N>();
+}
 
 template <class T, int NX, int TR, int TC, int RW, int MODE>
 __global__ __launch_bounds__((RW / 2) * (NX / row_elems<T, NX>()), (min_waves<T, NX>())) void row_kernel(const SweepArgs<T>* __restrict__ argv, int k_local,
@@ -642,7 +650,7 @@ template <class T>
 __device__ __forceinline__ cx<T> cconj(cx<T> v) { return cx<T>{v.re, -v.im}; }
 
 template <class T, int NY, int TR, int TC, int MODE, int FK>
-__global__ __launch_bounds__(TC * (NY / col_elems<T, NY>()), (col_min_waves<T, NY>())) void col_kernel(const SweepArgs<T>* __restrict__ argv, int k_local,
+__global__ __launch_bounds__(TC * (NY / col_elems<T, NY>()), (col_waves<T, NY, MODE>())) void col_kernel(const SweepArgs<T>* __restrict__ argv, int k_local,
     cx<T>* __restrict__ spec, double lam_init) {
   const SweepArgs<T>& a = argv[blockIdx.y];  // one map per grid row
   constexpr int E = col_elems<T, NY>();
