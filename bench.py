@@ -11,7 +11,8 @@ value = sweeps / second over the timed steps (map-sweeps/s).
 
 Also printed, on the same JSON line:
   roofline      the dominant kernel (column pass), algorithmic bytes per launch
-                / its mean duration from HIP events on the solve stream
+                / its mean duration from HIP events on the solve stream; also
+                the rate with the residual checked once at the end
   time_to_rtol  wall time of a zero-start solve to rho <= 1e-6 (the paper's
                 residual, observed pixels) with the augmented chain: float64
                 throughout (adaptive cooling lambda^0.97 and lambda^0.9, and the
@@ -19,6 +20,9 @@ Also printed, on the same JSON line:
                 residuals (wf_solve_refined); each with the per-sweep roofline of
                 its kernels; plus a float64 run whose stop test also asks the
                 masked part rho_mask <= 1e-6 (bounded sweep budget)
+  time_to_rtol_512  the same for the 512^2 map without a mask (float64, and
+                float32 refined), with the float64 field's distance to the
+                CPU oracle's own solve when the CPU leg runs
   batch         48 maps of three sizes (16 each of 256^2, 768^2, 1536^2) in
                 one batched solve (shared launches, replayed HIP graph), against
                 the same maps solved one after the other
@@ -336,6 +340,56 @@ def bench_stop_full(wf, torch, ctx64, args64, out64, entry):
           shrink=0.97, stop="hypot(rho, rho_mask) <= 1e-6, budget 40000 sweeps")
 
 
+def bench_c2(wf, synth, torch, dev):
+    """The 512^2 workload without a mask: zero-start solves to rho <= 1e-6,
+    float64 augmented chain (lambda^0.97 from 1e4, residual every 16) and the
+    float32-refined route of the 2048^2 section.  Returns the entries and the
+    float64 solution (host), which the CPU leg compares with the oracle's own
+    solve of the same schedule."""
+    p = synth.named_config("c2")
+    n = p.d.shape[0]
+
+    def t64(x):
+        return torch.tensor(np.ascontiguousarray(x), dtype=torch.float64, device=dev)
+    args = (t64(p.d), t64(p.s_k), t64(p.n_pix), t64(p.p_oof), t64(p.p_stripe), None)
+    ctx64 = wf.Context(n, n, "f64", device=dev)
+    ctx32 = wf.Context(n, n, "f32", device=dev)
+    out = {}
+    sch = wf.Schedule(lambda0=1.0e4, shrink=0.97, rtol=1e-6, max_sweeps=100000, monitor_every=16,
+                      chain="augmented")
+    ctx64.solve(*args, schedule=sch)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s64, r, _ = ctx64.solve(*args, schedule=sch)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    out["f64_shrink0.97"] = {"status": r["status"], "sweeps": r["sweeps"], "seconds": round(dt, 4),
+                             "rho": r["rho"], "map_sweeps_per_s": round(r["sweeps"] / dt, 1)}
+    first = wf.Schedule(lambda0=1.0e4, shrink=0.8, rtol=1e-3, max_sweeps=30000, monitor_every=8,
+                        chain="augmented")
+    corr = wf.Schedule(lambda0=300.0, shrink=0.8, rtol=0.1, max_sweeps=30000, monitor_every=8,
+                       chain="augmented")
+    wf.solve_refined(ctx32, ctx64, *args, first=first, corr=corr, max_rounds=4, rtol=1e-6)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s32, r, _ = wf.solve_refined(ctx32, ctx64, *args, first=first, corr=corr, max_rounds=4,
+                                 rtol=1e-6)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    out["f32_refined"] = {"status": r["status"], "sweeps": r["sweeps"], "seconds": round(dt, 4),
+                          "rho": r["rho"], "rounds": r["refine_rounds"],
+                          "map_sweeps_per_s": round(r["sweeps"] / dt, 1)}
+    s64 = s64.cpu().numpy()
+    out["f32_refined"]["rel_diff_to_f64"] = float(np.linalg.norm(s32.cpu().numpy() - s64)
+                                                  / np.linalg.norm(s64))
+    for k, v in out.items():
+        print(f"[bench] 512x512 to 1e-6 ({k}): {v['seconds']:.4f}s, {v['sweeps']} sweeps, "
+              f"rho {v['rho']:.2e}", file=sys.stderr, flush=True)
+    ctx64.close()
+    ctx32.close()
+    return out, s64
+
+
 def bench_section4(wf, torch, dev, p, n):
     """The two uses of the solver that Section 4 names, on the same 2048^2
     map, float64 augmented chain to rho <= 1e-6: the approximate
@@ -380,8 +434,9 @@ def cpu_time_to_rtol(oracle, synth, p, n, ttr, budget):
     cooling from 1e4 by lambda^0.97, residual every 16 sweeps) on the 64^2
     and 512^2 workloads, and at the benchmark's map an extrapolation: its
     measured per-sweep time of the same chain times the sweeps the GPU's
-    float64 solve of that schedule needed."""
-    res = {}
+    float64 solve of that schedule needed.  Also returns the oracle's
+    solutions by workload."""
+    res, sols = {}, {}
     sched = oracle.AdaptiveSchedule(lam0=1.0e4, shrink=0.97)
     for name, q in (("64x64", synth.named_config("c1")), ("512x512", synth.named_config("c2"))):
         t0 = time.perf_counter()
@@ -390,6 +445,7 @@ def cpu_time_to_rtol(oracle, synth, p, n, ttr, budget):
         dt = time.perf_counter() - t0
         res[name] = {"seconds": round(dt, 3), "sweeps": r.sweeps, "converged": bool(r.converged),
                      "rho": r.trace[-1][2]}
+        sols[name] = r.s
         print(f"[bench] cpu oracle to 1e-6 at {name}: {dt:.1f} s, {r.sweeps} sweeps",
               file=sys.stderr, flush=True)
     st = oracle.setup(p, oracle.Settings(chain="augmented"))
@@ -408,7 +464,7 @@ def cpu_time_to_rtol(oracle, synth, p, n, ttr, budget):
                        "seconds": round(per * gpu_sweeps, 1) if gpu_sweeps else None,
                        "note": "oracle per-sweep time of the augmented chain (monitor excluded) "
                                "times the GPU float64 solve's sweep count with the same schedule"}
-    return res
+    return res, sols
 
 
 def main():
@@ -497,6 +553,15 @@ def main():
     dt = time.perf_counter() - t0
     ms_step = 1e3 * dt / a.steps
     value = sweeps / dt
+    # the same schedule with the residual checked once, at the end
+    sched1 = wf.Schedule(lambdas=lams, rtol=0.0, max_sweeps=a.sweeps, monitor_every=a.sweeps)
+    ctx.solve(*args, schedule=sched1, out=out)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for _ in range(a.steps):
+        ctx.solve(*args, schedule=sched1, out=out)
+    torch.cuda.synchronize()
+    value_once = a.steps * a.sweeps / (time.perf_counter() - t1)
     # kernel durations for the roofline: the same solve with per-kernel
     # events (recorded by the dispatches themselves; these launches run
     # directly instead of as the replayed chunk graph of the timed steps)
@@ -529,7 +594,8 @@ def main():
             "sweep_achieved": round((cb + row_bytes(n, n)) / ((col_ms + row_ms) * 1e-3) / 1e9, 1),
             "sweep_frac": round((cb + row_bytes(n, n)) / ((col_ms + row_ms) * 1e-3) / 1e9
                                 / HBM_PEAK_GBS, 4),
-            "monitor_mean_us": round(1e3 * kms[2] / max(kn[2], 1), 2)}
+            "monitor_mean_us": round(1e3 * kms[2] / max(kn[2], 1), 2),
+            "map_sweeps_per_s_monitor_once": round(value_once, 1)}
     # context for the fractions above: a plain device-to-device copy of the
     # column kernel's byte count (half read, half written), timed the same way
     cp_n = cb // 8
@@ -555,6 +621,10 @@ def main():
     sec4 = None
     if not a.skip_sec4:
         sec4 = bench_section4(wf, torch, dev, p, n)
+
+    c2, c2_s = None, None
+    if not a.skip_ttr:
+        c2, c2_s = bench_c2(wf, synth, torch, dev)
 
     batch = None
     if not a.skip_batch:
@@ -617,7 +687,11 @@ def main():
                "kind": "oracle",
                "sample": f"{k} float64 sweeps of the same {n}x{n} three-level problem "
                          f"({tcpu:.1f} s, scipy.fft workers={cores}); setup and monitor excluded"}
-        cpu["time_to_rtol"] = cpu_time_to_rtol(oracle, synth, p, n, ttr, a.cpu_seconds)
+        cpu["time_to_rtol"], cpu_s = cpu_time_to_rtol(oracle, synth, p, n, ttr, a.cpu_seconds)
+        if c2 is not None and "512x512" in cpu_s:
+            so = cpu_s["512x512"]
+            c2["f64_shrink0.97"]["rel_diff_to_oracle"] = float(np.linalg.norm(c2_s - so)
+                                                               / np.linalg.norm(so))
         print(f"[bench] cpu oracle: {k} sweeps in {tcpu:.1f}s", file=sys.stderr, flush=True)
 
     line = {
@@ -638,10 +712,11 @@ def main():
                                f"cooling schedule, monitor every {a.monitor_every}",
                    "map": [n, n], "sweeps_per_step": a.sweeps, "chain": a.chain,
                    "seed": 3, "tiling": ctx.tile,
-                   "tiling_ms_per_48_sweeps": {str(k): round(1e3 * v, 3)
+                   "tiling_ms_per_48_sweeps": {str(k): round(v, 3)
                                                for k, v in tile_times.items()}},
         "roofline": roof,
         "time_to_rtol": ttr,
+        "time_to_rtol_512": c2,
         "batch": batch,
         "warm_start": warm,
         "section4": sec4,
