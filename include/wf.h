@@ -247,8 +247,10 @@ wf_status wf_solve_refined(void* ctx32, void* ctx64, const wf_inputs* in,
  * Returns the most severe error of any map, else
  * WF_NOT_CONVERGED if any map ran out of sweeps, else WF_OK; per-map status
  * is in reps[i].status.  Input errors are found before any sweep runs.
- * Allocates its per-call device buffers and graph and frees them before it
- * returns; synchronises stream. */
+ * The per-map schedules, argument blocks and the pinned read-back ring live
+ * in a workspace of ctxs[0], allocated on its first batch and grown only
+ * when a larger batch comes (freed with that context); the recorded graph,
+ * its streams and events are created per call.  Synchronises stream. */
 wf_status wf_solve_batch(void* const* ctxs, int32_t n, const wf_inputs* inputs,
                          const wf_schedule* sch, const void* const* s_init, void* const* s_out,
                          wf_report* reps, hipStream_t stream);

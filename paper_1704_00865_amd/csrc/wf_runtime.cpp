@@ -86,6 +86,14 @@ struct Ctx {
   void* ref_out = nullptr;
   void* ref_init = nullptr;  // float32 copy of a warm start of round 0
   void* ref_margs = nullptr;
+  // wf_solve_batch's per-call arrays when this context is a batch's first:
+  // per-map device schedules, argument blocks and controller arguments
+  // (device), and the ring the host reads the schedules back into (pinned);
+  // kept between calls and grown when a larger batch comes
+  void* batch_dev = nullptr;
+  size_t batch_dev_bytes = 0;
+  void* batch_host = nullptr;
+  size_t batch_host_bytes = 0;
   // one chunk of the single-map solve recorded as a HIP graph on cap_stream,
   // replayed for every chunk; valid for the (K, last sweep of the budget
   // within a chunk, tiling, chain kind) it was recorded with
@@ -171,6 +179,8 @@ void free_ctx(Ctx* c) {
                   c->ref_sk, c->ref_poof, c->ref_pst, c->ref_out, c->ref_init, c->ref_margs};
   for (void* p : bufs)
     if (p) (void)hipFree(p);
+  if (c->batch_dev) (void)hipFree(c->batch_dev);
+  if (c->batch_host) (void)hipHostFree(c->batch_host);
   if (c->h_ring) (void)hipHostFree(c->h_ring);
   if (c->h_stats) (void)hipHostFree(c->h_stats);
   if (c->h_args) (void)hipHostFree(c->h_args);
@@ -762,7 +772,8 @@ wf_status solve_batch_t(Ctx** ctxs, int n, const wf_inputs* ins, const wf_schedu
                         const void* const* s_init, void* const* s_out, wf_report* reps,
                         hipStream_t user_st) {
   std::vector<MapRun<T>> runs(n);
-  // device buffers of this call: schedules, argument blocks, controller args
+  // this call's schedules, argument blocks and controller arguments, in the
+  // first context's batch workspace
   DevSched* dsch = nullptr;
   SweepArgs<T>* dargs = nullptr;
   MonArgs<T>* dmargs = nullptr;
@@ -786,11 +797,6 @@ wf_status solve_batch_t(Ctx** ctxs, int n, const wf_inputs* ins, const wf_schedu
     if (ev_in) (void)hipEventDestroy(ev_in);
     for (auto& e : ev_ring)
       if (e) (void)hipEventDestroy(e);
-    if (hring) (void)hipHostFree(hring);
-    if (dsch) (void)hipFree(dsch);
-    if (dargs) (void)hipFree(dargs);
-    if (dmargs) (void)hipFree(dmargs);
-    if (dctrl) (void)hipFree(dctrl);
   };
 #define BT(expr)                          \
   do {                                    \
@@ -800,11 +806,35 @@ wf_status solve_batch_t(Ctx** ctxs, int n, const wf_inputs* ins, const wf_schedu
       return from_hip(e_);                \
     }                                     \
   } while (0)
-  BT(hipMalloc((void**)&dsch, (size_t)n * sizeof(DevSched)));
-  BT(hipMalloc((void**)&dargs, (size_t)n * sizeof(SweepArgs<T>)));
-  BT(hipMalloc((void**)&dmargs, (size_t)n * sizeof(MonArgs<T>)));
-  BT(hipMalloc((void**)&dctrl, (size_t)n * sizeof(CtrlArgs)));
-  BT(hipHostMalloc((void**)&hring, (size_t)kRing * n * sizeof(DevSched), hipHostMallocDefault));
+  {
+    auto al = [](size_t b) { return (b + 255) / 256 * 256; };
+    const size_t o1 = al((size_t)n * sizeof(DevSched));
+    const size_t o2 = o1 + al((size_t)n * sizeof(SweepArgs<T>));
+    const size_t o3 = o2 + al((size_t)n * sizeof(MonArgs<T>));
+    const size_t need = o3 + al((size_t)n * sizeof(CtrlArgs));
+    const size_t need_h = (size_t)kRing * n * sizeof(DevSched);
+    Ctx* w = ctxs[0];
+    if (w->batch_dev_bytes < need) {
+      if (w->batch_dev) (void)hipFree(w->batch_dev);
+      w->batch_dev = nullptr;
+      w->batch_dev_bytes = 0;
+      BT(hipMalloc(&w->batch_dev, need));
+      w->batch_dev_bytes = need;
+    }
+    if (w->batch_host_bytes < need_h) {
+      if (w->batch_host) (void)hipHostFree(w->batch_host);
+      w->batch_host = nullptr;
+      w->batch_host_bytes = 0;
+      BT(hipHostMalloc(&w->batch_host, need_h, hipHostMallocDefault));
+      w->batch_host_bytes = need_h;
+    }
+    char* base = (char*)w->batch_dev;
+    dsch = (DevSched*)base;
+    dargs = (SweepArgs<T>*)(base + o1);
+    dmargs = (MonArgs<T>*)(base + o2);
+    dctrl = (CtrlArgs*)(base + o3);
+    hring = (DevSched*)w->batch_host;
+  }
   for (int i = 0; i < n; ++i) BT(enqueue_stats<T>(ctxs[i], &ins[i], user_st));
   BT(hipStreamSynchronize(user_st));
   for (int i = 0; i < n; ++i) {
