@@ -1196,16 +1196,16 @@ __global__ __launch_bounds__(kRWM * (NX / mon_elems<NX>())) void mon_row_kernel(
   // kernel, where the same prefetch made it slower)
   const int r = tid / NT, t = tid - r * NT;
   const int y = y0 + r;
+  // (the white variance is Nbar_2 + nw_off on observed pixels: no read of
+  // the caller's N_pix, a quarter of this pass's bytes)
   const WF_GLOBAL T* mn2 = gmem(m.nbar2);
-  const WF_GLOBAL T* mnp = gmem(m.npix);
   const WF_GLOBAL T* md = gmem(m.d);
-  T pn2[E], pnp[E], pdd[E];
+  T pn2[E], pdd[E];
   if (mode != MON_OUTPUT) {
 #pragma unroll
     for (int q = 0; q < E; ++q) {
       const size_t i = (size_t)y * NX + t + NT * q;
       pn2[q] = mn2[i];
-      pnp[q] = mnp[i];
       pdd[q] = md[i];
     }
   }
@@ -1254,7 +1254,7 @@ __global__ __launch_bounds__(kRWM * (NX / mon_elems<NX>())) void mon_row_kernel(
     if (mode == MON_OUTPUT) {
       s_out[i] = (T)yv;
     } else if (pn2[q] >= (T)0) {
-      const double dd = yv + (double)pnp[q] * xv - (double)pdd[q];
+      const double dd = yv + ((double)pn2[q] + m.nw_off) * xv - (double)pdd[q];
       a_dd += dd * dd;
       if (mode == MON_REFINE) gmem(m.rout)[i] = (float)(-dd);
     } else {

@@ -110,8 +110,8 @@ struct MonArgs {
   const T* sy;          // [kx][ky] S + N_Fourier
   const T* sig;         // [kx][ky] S
   const T* d;           // [ny][nx]
-  const T* npix;        // [ny][nx] caller's white variance
   const T* nbar2;       // [ny][nx] sign marks the mask
+  double nw_off;        // white variance = nbar2 + nw_off on observed pixels
   void* Mx;             // cx<T> monitor transit, tiled [y/kTRM][kx/kTCM][kTRM][kTCM]
   void* My;
   const void* twx;      // cx<T> twiddle tables (natural order)

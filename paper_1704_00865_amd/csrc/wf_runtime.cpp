@@ -386,7 +386,7 @@ MonArgs<T> mon_args(Ctx* c, const wf_inputs* in, const Chain& ch) {
   m.sy = (const T*)c->sy;
   m.sig = (const T*)c->sig;
   m.d = (const T*)in->d;
-  m.npix = (const T*)in->n_pix;
+  m.nw_off = ch.phi + ch.tauW;  // the offset the set-up subtracted from N_pix
   m.nbar2 = (const T*)c->nbar2;
   m.Mx = c->Mx;
   m.My = c->My;
