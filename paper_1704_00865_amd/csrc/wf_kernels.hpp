@@ -23,10 +23,14 @@ enum FourierKind : int32_t {
 };
 
 // ROW_SWEEP_J / COL_SWEEP_J: a sweep that also sums the joint objective's
-// terms (eqn 2mess_prob) when it is the last sweep of its chunk
+// terms (eqn 2mess_prob) when it is the last sweep of its chunk; the column
+// variant then also runs the monitor's column transforms into Mx, My
 enum RowMode : int32_t { ROW_SWEEP = 0, ROW_R2C = 1, ROW_C2R = 2, ROW_SWEEP_J = 3 };
 enum ColMode : int32_t { COL_SWEEP = 0, COL_FWD_OUT = 1, COL_INV_IN = 2, COL_INIT = 3,
                          COL_SWEEP_J = 4 };
+// MON_RESIDUAL: residual sums of the state after a chunk (during a solve the
+// column pass of this mode runs inside the chunk's last column sweep, and
+// only the row kernel is launched).  MON_OUTPUT: the output field.
 // MON_REFINE: the residual sums of MON_RESIDUAL and the float32 right-hand
 // side d - d_rec (zero on masked pixels) to rout.
 enum MonMode : int32_t { MON_RESIDUAL = 0, MON_OUTPUT = 1, MON_REFINE = 3 };
