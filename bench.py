@@ -179,18 +179,12 @@ def bench_batch(wf, synth, torch, dev, a):
                 p_stripe=t(p.p_stripe)) for p in probs]
     ctxs = [wf.Context(p.d.shape[0], p.d.shape[1], "f32", device=dev) for p in probs]
     outs = [torch.empty(p.d.shape, dtype=torch.float32, device=dev) for p in probs]
-    # autotune one map of each size; its tiling serves the size class
-    tiles = {}
-    for c, pb in zip(ctxs, pbs):
-        key = (c.ny, c.nx)
-        if key not in tiles:
-            times = c.autotune(pb["d"], pb["s_k"], pb["n_pix"], pb["p_oof"], pb["p_stripe"])
-            tiles[key] = (c.tile, times)
-            print(f"[bench] batch {key[0]}x{key[1]}: tiling {c.tile} "
-                  f"({', '.join(f'{k}: {v:.2f}' for k, v in times.items())} ms)",
-                  file=sys.stderr, flush=True)
-        else:
-            c.set_tile(tiles[key][0])
+    # each size class is tuned on a batched probe of its own maps
+    tiles = wf.autotune_batch(ctxs, pbs, outs=outs)
+    for key, (chosen, times) in tiles.items():
+        print(f"[bench] batch {key[0]}x{key[1]}: tiling {chosen} "
+              f"({', '.join(f'{k}: {v:.2f}' for k, v in times.items())} ms)",
+              file=sys.stderr, flush=True)
     lams = cooling_lambdas(400, a.sweeps, 1.0e4)
     sched = wf.Schedule(lambdas=lams, rtol=0.0, max_sweeps=a.sweeps,
                         monitor_every=a.monitor_every)
@@ -229,9 +223,10 @@ def bench_batch(wf, synth, torch, dev, a):
             "speedup_vs_one_at_a_time": round(dts / dtb, 3),
             "algorithmic_GBps": round(gbs, 1), "frac_of_hbm_peak": round(gbs / HBM_PEAK_GBS, 4),
             "tilings": {f"{k[0]}x{k[1]}": {"chosen": v[0],
-                                           "ms_per_48_sweeps": {str(t): round(m, 3)
-                                                                for t, m in v[1].items()}}
+                                           "ms_per_probe": {str(t): round(m, 3)
+                                                            for t, m in v[1].items()}}
                         for k, v in tiles.items()},
+            "tiling_probe": "48 sweeps of the class's 16 maps in one batched solve",
             "note": "sweep kernels only in the algorithmic bytes (monitor every "
                     f"{a.monitor_every} sweeps is extra work inside the time)"}
 

@@ -304,6 +304,27 @@ int32_t wf_ctx_get_tile(void* ctx);
 wf_status wf_autotune(void* ctx, const wf_inputs* in, int32_t sweeps, void* scratch, double* ms,
                       int32_t* best, hipStream_t stream);
 
+/* Autotuner for batches (not from the paper): the best tiling of a map
+ * solved alone can differ from that of many maps of its shape sharing each
+ * launch.  For each group of maps of one shape, times short batched solves
+ * of that group alone (wf_solve_batch over its maps, the probe schedule of
+ * wf_autotune) in every tiling built for the shape, and leaves the group's
+ * contexts on the fastest.
+ *   ctxs, n, inputs  as for wf_solve_batch;
+ *   sweeps           probe length, 1 <= sweeps <= 4096;
+ *   s_out[n]         HOST array of DEVICE buffers [ny_i*nx_i] of the contexts'
+ *                    precision, overwritten with the probe solves' output;
+ *   ms               HOST [n * wf_tile_count()]: ms[i*count + t] is the time in
+ *                    milliseconds of one probe solve of map i's group in tiling
+ *                    t (-1: not built), or NULL;
+ *   best             HOST [n], receives the tiling each context is left on,
+ *                    or NULL.
+ * Synchronises stream.  A solve error is returned at once: the group being
+ * tuned keeps its previous tilings, the groups before it their new ones. */
+wf_status wf_autotune_batch(void* const* ctxs, int32_t n, const wf_inputs* inputs,
+                            int32_t sweeps, void* const* s_out, double* ms, int32_t* best,
+                            hipStream_t stream);
+
 /* Sizes the library was built for, and its precision support. */
 int32_t wf_supported(int32_t ny, int32_t nx, int32_t precision);
 

@@ -73,7 +73,8 @@ class _Report(ctypes.Structure):
 EXPORTS = ("wf_ctx_create", "wf_ctx_destroy", "wf_schedule_default", "wf_solve", "wf_rfft2",
            "wf_irfft2", "wf_ctx_set_profiling", "wf_supported", "wf_strerror", "wf_tile_count",
            "wf_ctx_set_tile", "wf_ctx_get_tile", "wf_inverse_noise_weight", "wf_solve_batch",
-           "wf_solve_noalloc", "wf_noalloc_scratch_bytes", "wf_solve_refined", "wf_autotune")
+           "wf_solve_noalloc", "wf_noalloc_scratch_bytes", "wf_solve_refined", "wf_autotune",
+           "wf_autotune_batch")
 
 
 def load():
@@ -118,6 +119,10 @@ def load():
     lib.wf_autotune.argtypes = [vp, ctypes.POINTER(_Inputs), i32, vp,
                                 ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i32), vp]
     lib.wf_autotune.restype = i32
+    lib.wf_autotune_batch.argtypes = [ctypes.POINTER(vp), i32, ctypes.POINTER(_Inputs), i32,
+                                      ctypes.POINTER(vp), ctypes.POINTER(ctypes.c_double),
+                                      ctypes.POINTER(i32), vp]
+    lib.wf_autotune_batch.restype = i32
     lib.wf_rfft2.argtypes = [vp, vp, vp, vp]
     lib.wf_rfft2.restype = i32
     lib.wf_irfft2.argtypes = [vp, vp, vp, vp]
@@ -499,6 +504,51 @@ def solve_batch(contexts, problems, *, schedule: Schedule = Schedule(), outs=Non
     import torch
     lib = load()
     n = len(contexts)
+    inps, handles, optrs, iptrs, res = _batch_args(contexts, problems, outs, s_inits)
+    sch, keep = schedule._c()
+    reps = (_Report * n)()
+    dev = contexts[0].device
+    with torch.cuda.device(dev):
+        st = lib.wf_solve_batch(handles, n, inps, ctypes.byref(sch),
+                                iptrs if s_inits is not None else None, optrs, reps,
+                                _stream_ptr(torch, dev))
+    del keep
+    if st < 0:
+        raise WFError(st, "wf_solve_batch")
+    return res, [_report(r) for r in reps]
+
+
+def autotune_batch(contexts, problems, *, outs=None, sweeps=48):
+    """``wf_autotune_batch``: for each shape among the maps, time short
+    batched solves of the maps of that shape in every built tiling and keep
+    the fastest on their contexts.  Arguments as for ``solve_batch`` (outs,
+    if given, are overwritten by the probes).  Returns {(ny, nx): (chosen
+    tiling, {tiling: ms per probe solve})}."""
+    import torch
+    lib = load()
+    n = len(contexts)
+    inps, handles, optrs, _, probe_outs = _batch_args(contexts, problems, outs, None)
+    nt = lib.wf_tile_count()
+    ms = (ctypes.c_double * (n * nt))()
+    best = (ctypes.c_int32 * n)()
+    dev = contexts[0].device
+    with torch.cuda.device(dev):
+        st = lib.wf_autotune_batch(handles, n, inps, int(sweeps), optrs, ms, best,
+                                   _stream_ptr(torch, dev))
+    if st < 0:
+        raise WFError(st, "wf_autotune_batch")
+    out = {}
+    for i, ctx in enumerate(contexts):
+        out.setdefault((ctx.ny, ctx.nx), (best[i], {t: ms[i * nt + t] for t in range(nt)
+                                                   if ms[i * nt + t] >= 0}))
+    return out
+
+
+def _batch_args(contexts, problems, outs, s_inits):
+    """ctypes arrays of a batch call: per-map inputs, context handles, output
+    and warm-start pointers (outputs allocated where outs has None)."""
+    import torch
+    n = len(contexts)
     if n != len(problems) or n < 1:
         raise ValueError("need one problem per context")
     if outs is None:
@@ -530,17 +580,7 @@ def solve_batch(contexts, problems, *, schedule: Schedule = Schedule(), outs=Non
         if si is not None:
             ctx._check(si, (ny, nx), "s_init")
             iptrs[i] = si.data_ptr()
-    sch, keep = schedule._c()
-    reps = (_Report * n)()
-    dev = contexts[0].device
-    with torch.cuda.device(dev):
-        st = lib.wf_solve_batch(handles, n, inps, ctypes.byref(sch),
-                                iptrs if s_inits is not None else None, optrs, reps,
-                                _stream_ptr(torch, dev))
-    del keep
-    if st < 0:
-        raise WFError(st, "wf_solve_batch")
-    return res, [_report(r) for r in reps]
+    return inps, handles, optrs, iptrs, res
 
 
 def rfft2(x):

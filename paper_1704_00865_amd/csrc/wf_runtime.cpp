@@ -1382,16 +1382,12 @@ wf_status wf_ctx_set_tile(void* ctx, int32_t tile) {
   return WF_OK;
 }
 
-wf_status wf_autotune(void* ctx, const wf_inputs* in, int32_t sweeps, void* scratch,
-                      double* ms, int32_t* best, hipStream_t stream) {
-  Ctx* c = (Ctx*)ctx;
-  if (!c || !in || !scratch || sweeps < 1 || sweeps > 4096) return WF_EINVAL;
-  if (!in->d || !in->s_k || !in->n_pix) return WF_EINVAL;
-  int dev = 0;
-  if (hipGetDevice(&dev) != hipSuccess || dev != c->device) return WF_EINVAL;
-  // a cooling ramp from 1e3 over the probe's first half (the sweep kernels
-  // do not depend on lambda's value; this keeps the probe a valid solve)
-  std::vector<double> lam(sweeps);
+namespace {
+// the autotuners' probe: a cooling ramp from 1e3 over the probe's first half
+// (the sweep kernels do not depend on lambda's value; this keeps the probe a
+// valid solve), no stop before the budget, monitor every 16 sweeps
+wf_schedule probe_schedule(int sweeps, std::vector<double>& lam) {
+  lam.resize(sweeps);
   for (int k = 0; k < sweeps; ++k)
     lam[k] = k < sweeps / 2 ? std::pow(1.0e3, 1.0 - 2.0 * k / sweeps) : 1.0;
   wf_schedule sch;
@@ -1401,7 +1397,20 @@ wf_status wf_autotune(void* ctx, const wf_inputs* in, int32_t sweeps, void* scra
   sch.n_lambda = sweeps;
   sch.rtol = 0.0;
   sch.max_sweeps = sweeps;
-  sch.monitor_every = std::min(16, (int)sweeps);
+  sch.monitor_every = std::min(16, sweeps);
+  return sch;
+}
+}  // namespace
+
+wf_status wf_autotune(void* ctx, const wf_inputs* in, int32_t sweeps, void* scratch,
+                      double* ms, int32_t* best, hipStream_t stream) {
+  Ctx* c = (Ctx*)ctx;
+  if (!c || !in || !scratch || sweeps < 1 || sweeps > 4096) return WF_EINVAL;
+  if (!in->d || !in->s_k || !in->n_pix) return WF_EINVAL;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev != c->device) return WF_EINVAL;
+  std::vector<double> lam;
+  const wf_schedule sch = probe_schedule(sweeps, lam);
   const int old_tile = c->tile, old_prof = c->profiling;
   c->profiling = 0;
   double best_ms = INFINITY;
@@ -1430,6 +1439,77 @@ wf_status wf_autotune(void* ctx, const wf_inputs* in, int32_t sweeps, void* scra
   c->profiling = old_prof;
   c->tile = (err == WF_OK && best_tile >= 0) ? best_tile : old_tile;
   if (best) *best = c->tile;
+  return err;
+}
+
+wf_status wf_autotune_batch(void* const* ctxs, int32_t n, const wf_inputs* inputs,
+                            int32_t sweeps, void* const* s_out, double* ms, int32_t* best,
+                            hipStream_t stream) {
+  if (!ctxs || !inputs || !s_out || n < 1 || n > WF_BATCH_MAX || sweeps < 1 || sweeps > 4096)
+    return WF_EINVAL;
+  for (int i = 0; i < n; ++i)
+    if (!ctxs[i]) return WF_EINVAL;
+  std::vector<double> lam;
+  const wf_schedule sch = probe_schedule(sweeps, lam);
+  std::vector<char> grouped(n, 0);
+  wf_status err = WF_OK;
+  for (int i = 0; i < n && err == WF_OK; ++i) {
+    if (grouped[i]) continue;
+    // the maps of map i's shape, tuned together
+    const Ctx* ci = (const Ctx*)ctxs[i];
+    std::vector<int> g;
+    for (int j = i; j < n; ++j) {
+      const Ctx* cj = (const Ctx*)ctxs[j];
+      if (!grouped[j] && cj->ny == ci->ny && cj->nx == ci->nx) {
+        g.push_back(j);
+        grouped[j] = 1;
+      }
+    }
+    const int m = (int)g.size();
+    std::vector<void*> gc(m), go(m);
+    std::vector<wf_inputs> gi(m);
+    std::vector<int> old(m);
+    for (int k = 0; k < m; ++k) {
+      gc[k] = ctxs[g[k]];
+      go[k] = s_out[g[k]];
+      gi[k] = inputs[g[k]];
+      old[k] = ((Ctx*)gc[k])->tile;
+    }
+    double tms[kNumTiles];
+    double best_ms = INFINITY;
+    int best_tile = -1;
+    for (int tile = 0; tile < kNumTiles; ++tile) {
+      tms[tile] = -1.0;
+      bool built = true;
+      for (void* c : gc) built = built && wf_ctx_set_tile(c, tile) == WF_OK;
+      if (!built) continue;
+      // warm-up (records the batch's graph), then two timed batched solves
+      wf_status st = wf_solve_batch(gc.data(), m, gi.data(), &sch, nullptr, go.data(), nullptr,
+                                    stream);
+      const auto t0 = std::chrono::steady_clock::now();
+      for (int rep = 0; rep < 2 && st >= 0; ++rep)
+        st = wf_solve_batch(gc.data(), m, gi.data(), &sch, nullptr, go.data(), nullptr, stream);
+      const double t = std::chrono::duration<double, std::milli>(
+                           std::chrono::steady_clock::now() - t0).count() / 2.0;
+      if (st < 0) {
+        err = st;
+        break;
+      }
+      tms[tile] = t;
+      if (t < best_ms) {
+        best_ms = t;
+        best_tile = tile;
+      }
+    }
+    for (int k = 0; k < m; ++k) {
+      Ctx* c = (Ctx*)gc[k];
+      c->tile = (err == WF_OK && best_tile >= 0) ? best_tile : old[k];
+      if (ms)
+        for (int tile = 0; tile < kNumTiles; ++tile) ms[(size_t)g[k] * kNumTiles + tile] = tms[tile];
+    }
+  }
+  if (best)
+    for (int i = 0; i < n; ++i) best[i] = ((Ctx*)ctxs[i])->tile;
   return err;
 }
 

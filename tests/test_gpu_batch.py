@@ -186,3 +186,37 @@ def test_batch_warm_starts_match_single(gpu_lib, prec):
         s1, _, _ = ctx.solve(pb["d"], pb["s_k"], pb["n_pix"], pb["p_oof"], pb["p_stripe"],
                              pb.get("mask"), schedule=sched, s_init=inits[i])
         assert torch.equal(outs[i], s1), i
+
+
+def test_batch_autotuner_tunes_each_shape_on_its_batch(gpu_lib):
+    """wf_autotune_batch: for each shape, every built tiling is timed on a
+    batched probe of that shape's maps and their contexts keep the fastest;
+    the batch solved afterwards equals the same batch in the default tiling
+    bit for bit (a tiling moves data, it does not change the arithmetic)."""
+    import torch
+    sizes = [256, 256, 256, 768, 768]
+    probs = [synth.make_problem(n, n, 900 + i, mask_frac=0.05) for i, n in enumerate(sizes)]
+    pbs = [_dict(p, "f32") for p in probs]
+    ctxs = [gpu_lib.Context(n, n, "f32") for n in sizes]
+    print("batch autotune 3 x 256^2 + 2 x 768^2", flush=True)
+    res = gpu_lib.autotune_batch(ctxs, pbs, sweeps=16)
+    nt = gpu_lib.load().wf_tile_count()
+    assert set(res) == {(256, 256), (768, 768)}
+    for (ny, nx), (chosen, times) in res.items():
+        print(f"  {ny}x{nx}: tiling {chosen}", {k: round(v, 3) for k, v in times.items()},
+              flush=True)
+        assert len(times) == nt  # every tiling is built at these lengths
+        assert chosen == min(times, key=times.get)
+        assert all(c.tile == chosen for c in ctxs if (c.ny, c.nx) == (ny, nx))
+    sched = gpu_lib.Schedule(lambdas=list(oracle.cooling_ramp(6, 12, 300.0)), rtol=0.0,
+                             max_sweeps=12, monitor_every=4)
+    outs, _ = gpu_lib.solve_batch(ctxs, pbs, schedule=sched)
+    ref_ctxs = [gpu_lib.Context(n, n, "f32") for n in sizes]
+    ref, _ = gpu_lib.solve_batch(ref_ctxs, pbs, schedule=sched)
+    for i, (a, b) in enumerate(zip(outs, ref)):
+        assert torch.equal(a, b), i
+    # float64 contexts: the default tiling is the only one built
+    c64 = [gpu_lib.Context(64, 64, "f64") for _ in range(2)]
+    q = [_dict(synth.make_problem(64, 64, 910 + i), "f64") for i in range(2)]
+    r64 = gpu_lib.autotune_batch(c64, q, sweeps=4)
+    assert list(r64) == [(64, 64)] and r64[(64, 64)][0] == 1 and list(r64[(64, 64)][1]) == [1]
