@@ -129,28 +129,55 @@ __device__ double block_reduce(double v, double* sh) {
 // ---------------------------------------------------------------------------
 // setup: validation statistics
 // ---------------------------------------------------------------------------
+// Four consecutive pixels 4 i4 .. 4 i4 + 3 (n is a multiple of 4: every
+// side is at least 64), in one vector access when VEC (the caller's arrays
+// are aligned to it), else element by element; the values and their order
+// are the same either way.
+template <class T>
+using vec4 = T __attribute__((ext_vector_type(4)));
+typedef unsigned char u8x4 __attribute__((ext_vector_type(4)));
+template <bool VEC, class T>
+__device__ __forceinline__ vec4<T> load4(const T* __restrict__ p, int64_t i4) {
+  if constexpr (VEC) return reinterpret_cast<const vec4<T>*>(p)[i4];
+  else return vec4<T>{p[4 * i4], p[4 * i4 + 1], p[4 * i4 + 2], p[4 * i4 + 3]};
+}
+template <bool VEC, class T>
+__device__ __forceinline__ void store4(T* __restrict__ p, int64_t i4, vec4<T> v) {
+  if constexpr (VEC) {
+    reinterpret_cast<vec4<T>*>(p)[i4] = v;
+  } else {
+#pragma unroll
+    for (int u = 0; u < 4; ++u) p[4 * i4 + u] = v[u];
+  }
+}
+
 // per block: n_obs, min N_pix(obs), max N_pix(obs), sum d^2 (obs),
 //            #non-finite (d or N_pix on observed), #N_pix <= 0 (observed)
-template <class T>
+template <class T, bool VEC>
 __global__ __launch_bounds__(256) void stats_pixels_kernel(const T* __restrict__ d,
                                                            const T* __restrict__ npix,
                                                            const uint8_t* __restrict__ mask,
                                                            int64_t n, double* __restrict__ part) {
   __shared__ double sh[16];
   double cnt = 0, mn = INFINITY, mx = -INFINITY, s2 = 0, bad = 0, badn = 0;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-       i += (int64_t)gridDim.x * blockDim.x) {
-    if (mask && mask[i] == 0) continue;
-    const double dv = (double)d[i], nv = (double)npix[i];
-    cnt += 1;
-    if (!isfinite(dv) || !isfinite(nv)) {
-      bad += 1;
-      continue;
+  for (int64_t i4 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i4 < n / 4;
+       i4 += (int64_t)gridDim.x * blockDim.x) {
+    const vec4<T> dq = load4<VEC>(d, i4), nq = load4<VEC>(npix, i4);
+    const u8x4 mq = mask ? load4<VEC>(mask, i4) : u8x4{1, 1, 1, 1};
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      if (mq[u] == 0) continue;
+      const double dv = (double)dq[u], nv = (double)nq[u];
+      cnt += 1;
+      if (!isfinite(dv) || !isfinite(nv)) {
+        bad += 1;
+        continue;
+      }
+      if (!(nv > 0)) badn += 1;
+      mn = fmin(mn, nv);
+      mx = fmax(mx, nv);
+      s2 += dv * dv;
     }
-    if (!(nv > 0)) badn += 1;
-    mn = fmin(mn, nv);
-    mx = fmax(mx, nv);
-    s2 += dv * dv;
   }
   cnt = block_reduce<RED_SUM>(cnt, sh);
   mn = block_reduce<RED_MIN>(mn, sh);
@@ -174,11 +201,11 @@ __global__ __launch_bounds__(256) void stats_spectra_kernel(const T* __restrict_
                                                             int ny, int nx, double* __restrict__ part) {
   __shared__ double sh[16];
   const int nh = nx / 2 + 1;
-  const int64_t n = (int64_t)ny * nh;
   double ms = INFINITY, mo = INFINITY, mf = INFINITY, bs = 0, bo = 0, bp = 0, asym = 0;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-       i += (int64_t)gridDim.x * blockDim.x) {
-    const int ky = (int)(i / nh), kx = (int)(i - (int64_t)ky * nh);
+  // block b takes rows b, b + gridDim.x, ...; its threads stride along a row
+  for (int ky = blockIdx.x; ky < ny; ky += gridDim.x)
+  for (int kx = threadIdx.x; kx < nh; kx += blockDim.x) {
+    const int64_t i = (int64_t)ky * nh + kx;
     const double s = (double)sk[i];
     if (!isfinite(s) || s < 0) bs += 1;
     ms = fmin(ms, s);
@@ -245,14 +272,18 @@ __global__ __launch_bounds__(512) void stats_finalize_kernel(const double* __res
 // ---------------------------------------------------------------------------
 // setup: per-pixel and per-mode coefficients
 // ---------------------------------------------------------------------------
-template <class T>
+template <class T, bool VEC>
 __global__ __launch_bounds__(256) void prep_pixels_kernel(const T* __restrict__ npix,
                                                           const uint8_t* __restrict__ mask, int64_t n,
                                                           double sub, T* __restrict__ nbar2) {
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-       i += (int64_t)gridDim.x * blockDim.x) {
-    const bool obs = !mask || mask[i] != 0;
-    nbar2[i] = obs ? (T)((double)npix[i] - sub) : (T)(-1);
+  for (int64_t i4 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i4 < n / 4;
+       i4 += (int64_t)gridDim.x * blockDim.x) {
+    const vec4<T> nq = load4<VEC>(npix, i4);
+    const u8x4 mq = mask ? load4<VEC>(mask, i4) : u8x4{1, 1, 1, 1};
+    vec4<T> o;
+#pragma unroll
+    for (int u = 0; u < 4; ++u) o[u] = mq[u] != 0 ? (T)((double)nq[u] - sub) : (T)(-1);
+    store4<true>(nbar2, i4, o);  // the context's own array: aligned
   }
 }
 
@@ -265,20 +296,40 @@ __global__ __launch_bounds__(256) void prep_pixels_kernel(const T* __restrict__ 
 //   sig = S
 
 
+// One block per 32 x 32 tile of modes: the caller's row-major [ky][kx]
+// spectra are read along k_x and staged in LDS, and the outputs are written
+// along k_y, so that both sides are coalesced.
+constexpr int kPrepTile = 32;
+
 template <class T>
 __global__ __launch_bounds__(256) void prep_spectra_kernel(const T* __restrict__ sk,
                                                            const T* __restrict__ poof,
                                                            const T* __restrict__ pst, PrepSpecArgs a,
                                                            T* __restrict__ sc, T* __restrict__ nbA,
                                                            T* __restrict__ sy, T* __restrict__ sig) {
+  constexpr int TT = kPrepTile;
+  __shared__ T ls[TT][TT + 1], lo[TT][TT + 1];  // [ky][kx] within the tile
   const int nh = a.nx / 2 + 1;
-  const int64_t n = (int64_t)a.ny * nh;
-  for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < n;
-       j += (int64_t)gridDim.x * blockDim.x) {
-    const int kx = (int)(j / a.ny), ky = (int)(j - (int64_t)kx * a.ny);
-    const int64_t i = (int64_t)ky * nh + kx;  // row-major source index
-    const double s = (double)sk[i];
-    double o = a.has_oof ? (double)poof[i] : 0.0;
+  const int kx0 = blockIdx.x * TT, ky0 = blockIdx.y * TT;
+  const int tx = threadIdx.x % TT, ty = threadIdx.x / TT;
+  constexpr int RS = 256 / TT;  // rows per step
+#pragma unroll
+  for (int r = ty; r < TT; r += RS) {
+    const int ky = ky0 + r, kx = kx0 + tx;
+    if (ky < a.ny && kx < nh) {
+      const int64_t i = (int64_t)ky * nh + kx;
+      ls[r][tx] = sk[i];
+      lo[r][tx] = a.has_oof ? poof[i] : (T)0;
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int r = ty; r < TT; r += RS) {
+    const int kx = kx0 + r, ky = ky0 + tx;
+    if (ky >= a.ny || kx >= nh) continue;
+    const int64_t j = (int64_t)kx * a.ny + ky;  // column-major output index
+    const double s = (double)ls[tx][r];
+    double o = (double)lo[tx][r];
     if (isinf(o)) o = kInfiniteCov;  // projected mode (see kInfiniteCov)
     const double st = (a.has_st && kx == 0) ? (double)a.nx * (double)pst[ky] : 0.0;
     const double nf = o + st;

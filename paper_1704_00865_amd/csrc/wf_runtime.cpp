@@ -26,7 +26,7 @@ using namespace wf;
 
 namespace {
 
-constexpr int kStatBlocks = 256;
+constexpr int kStatBlocks = 1024;  // blocks of the validation statistics (partials in c->part)
 constexpr int kRing = 4;   // pinned readback slots
 constexpr int kLag = 2;    // chunks between enqueue and the host's check
 constexpr int kProfSlots = 512;
