@@ -422,6 +422,36 @@ def test_bitwise_deterministic(gpu_lib):
     np.testing.assert_array_equal(ta, tb)
 
 
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+def test_unaligned_inputs_give_identical_results(gpu_lib, prec):
+    """The set-up passes read the caller's per-pixel arrays four values at a
+    time with vector loads when the pointers allow it, else one by one in the
+    same order: d and N_pix one element, and the mask one byte, past an
+    aligned address give the same solve bit for bit."""
+    import torch
+    p = synth.make_problem(256, 128, 5, mask_frac=0.1)
+    args = _tensors(p, prec)
+    d, sk, npix, poof, pst, mask = args
+
+    def shifted(t):
+        buf = torch.empty(t.numel() + 1, dtype=t.dtype, device=t.device)
+        v = buf[1:].view(t.shape)
+        v.copy_(t)
+        return v
+    un = (shifted(d), sk, shifted(npix), poof, pst, shifted(mask))
+    esz = 4 if prec == "f32" else 8
+    assert un[0].data_ptr() % (4 * esz) != 0 and un[5].data_ptr() % 4 != 0
+    ctx = gpu_lib.Context(256, 128, prec)
+    sched = gpu_lib.Schedule(lambdas=[1e3, 300.0, 100.0, 30.0, 10.0, 3.0, 1.0, 1.0], rtol=0.0,
+                             max_sweeps=8, monitor_every=4)
+    a, ra, ta = ctx.solve(*args, schedule=sched)
+    a = a.cpu().numpy().copy()
+    b, rb, tb = ctx.solve(*un, schedule=sched)
+    np.testing.assert_array_equal(a, b.cpu().numpy())
+    np.testing.assert_array_equal(ta, tb)
+    assert ra["d2"] == rb["d2"]
+
+
 @pytest.mark.parametrize("shape", [(2048, 2048), (1536, 768), (256, 256)])
 def test_tilings_give_identical_results(gpu_lib, shape):
     """Every transit-buffer tiling only moves data differently, so all of
