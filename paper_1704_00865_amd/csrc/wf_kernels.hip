@@ -272,10 +272,13 @@ __global__ __launch_bounds__(512) void stats_finalize_kernel(const double* __res
 // ---------------------------------------------------------------------------
 // setup: per-pixel and per-mode coefficients
 // ---------------------------------------------------------------------------
+// Also zeroes zb (n values: the transit buffer, whose nx/2 complex columns
+// per row hold as many values as the map has pixels) for the zero start.
 template <class T, bool VEC>
 __global__ __launch_bounds__(256) void prep_pixels_kernel(const T* __restrict__ npix,
                                                           const uint8_t* __restrict__ mask, int64_t n,
-                                                          double sub, T* __restrict__ nbar2) {
+                                                          double sub, T* __restrict__ nbar2,
+                                                          T* __restrict__ zb) {
   for (int64_t i4 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i4 < n / 4;
        i4 += (int64_t)gridDim.x * blockDim.x) {
     const vec4<T> nq = load4<VEC>(npix, i4);
@@ -283,7 +286,8 @@ __global__ __launch_bounds__(256) void prep_pixels_kernel(const T* __restrict__ 
     vec4<T> o;
 #pragma unroll
     for (int u = 0; u < 4; ++u) o[u] = mq[u] != 0 ? (T)((double)nq[u] - sub) : (T)(-1);
-    store4<true>(nbar2, i4, o);  // the context's own array: aligned
+    store4<true>(nbar2, i4, o);  // the context's own arrays: aligned
+    store4<true>(zb, i4, vec4<T>{(T)0, (T)0, (T)0, (T)0});
   }
 }
 
@@ -301,12 +305,17 @@ __global__ __launch_bounds__(256) void prep_pixels_kernel(const T* __restrict__ 
 // along k_y, so that both sides are coalesced.
 constexpr int kPrepTile = 32;
 
+// Also zeroes the three per-mode state arrays z0, z1, z2 (complex, same
+// layout) for the zero start.
 template <class T>
 __global__ __launch_bounds__(256) void prep_spectra_kernel(const T* __restrict__ sk,
                                                            const T* __restrict__ poof,
                                                            const T* __restrict__ pst, PrepSpecArgs a,
                                                            T* __restrict__ sc, T* __restrict__ nbA,
-                                                           T* __restrict__ sy, T* __restrict__ sig) {
+                                                           T* __restrict__ sy, T* __restrict__ sig,
+                                                           cx<T>* __restrict__ z0,
+                                                           cx<T>* __restrict__ z1,
+                                                           cx<T>* __restrict__ z2) {
   constexpr int TT = kPrepTile;
   __shared__ T ls[TT][TT + 1], lo[TT][TT + 1];  // [ky][kx] within the tile
   const int nh = a.nx / 2 + 1;
@@ -338,6 +347,10 @@ __global__ __launch_bounds__(256) void prep_spectra_kernel(const T* __restrict__
     else if (a.nbA_kind == 2) nbA[j] = (T)(nf + a.phi_nf - a.tauA);
     sy[j] = (T)(s + nf);
     sig[j] = (T)s;
+    const cx<T> zero = {(T)0, (T)0};
+    z0[j] = zero;
+    z1[j] = zero;
+    z2[j] = zero;
   }
 }
 

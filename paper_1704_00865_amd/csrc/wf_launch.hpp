@@ -46,9 +46,11 @@ hipError_t launch_stats(const T* d, const T* npix, const uint8_t* mask, const T*
                         const T* pst, int ny, int nx, double* part, int nblk, double* out_pix,
                         double* out_spec, hipStream_t st);
 template <class T>
+// per-pixel and per-mode coefficients; also zeroes the transit buffer zB and
+// the three per-mode state arrays zA, zD, zT (the zero start)
 hipError_t launch_prep(const T* npix, const uint8_t* mask, int ny, int nx, double sub, T* nbar2,
                        const T* sk, const T* poof, const T* pst, const PrepSpecArgs& pa, T* sc, T* nbA,
-                       T* sy, T* sig, hipStream_t st);
+                       T* sy, T* sig, void* zB, void* zA, void* zD, void* zT, hipStream_t st);
 
 template <class T>
 hipError_t launch_fill(T* x, int64_t n, double v, hipStream_t st);

@@ -488,7 +488,7 @@ wf_status map_setup(Ctx* c, const wf_inputs* in, const wf_schedule* s, const voi
   WF_TRY(launch_prep<T>((const T*)in->n_pix, in->mask, c->ny, c->nx, r.ch.phi + r.ch.tauW,
                         (T*)c->nbar2, (const T*)in->s_k, (const T*)in->p_oof,
                         (const T*)in->p_stripe, r.ch.pa, (T*)c->sc, (T*)c->nbA, (T*)c->sy,
-                        (T*)c->sig, st));
+                        (T*)c->sig, c->B, c->tA, c->dA, c->tB, st));
   // schedule: lambda per sweep and the device-side controller state
   const int K = s->monitor_every, maxs = s->max_sweeps;
   r.n_chunks = (maxs + K - 1) / K;
@@ -539,7 +539,6 @@ wf_status map_setup(Ctx* c, const wf_inputs* in, const wf_schedule* s, const voi
   r.m.out_chain = s->field_mode;
   r.ctrl = CtrlArgs{dsched, c->lam, c->part, c->ny / kRWM, c->trace, c->jpart, j_blocks(c)};
   // initial state (the single-map argument block is used for the warm start)
-  const size_t modes_b = (size_t)c->nh * c->ny * 2 * c->esz;
   if (s_init) {
     std::memcpy(c->h_args, &r.a, sizeof(r.a));
     WF_TRY(hipMemcpyAsync(c->d_args, c->h_args, sizeof(r.a), hipMemcpyHostToDevice, st));
@@ -548,12 +547,8 @@ wf_status map_setup(Ctx* c, const wf_inputs* in, const wf_schedule* s, const voi
     WF_TRY(launch_col<T>(c->tile, COL_INIT, r.a, (const SweepArgs<T>*)c->d_args, 1, 0, nullptr,
                          r.lam[0], st));
     WF_TRY(hipStreamSynchronize(st));
-  } else {
-    WF_TRY(hipMemsetAsync(c->B, 0, (size_t)c->ny * (c->nx / 2) * 2 * c->esz, st));
-    WF_TRY(hipMemsetAsync(c->tA, 0, modes_b, st));
-    WF_TRY(hipMemsetAsync(c->dA, 0, modes_b, st));
-    WF_TRY(hipMemsetAsync(c->tB, 0, modes_b, st));
   }
+  // (the zero start: the set-up's coefficient passes zeroed B and the state)
   return WF_OK;
 }
 
