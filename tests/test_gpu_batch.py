@@ -220,3 +220,21 @@ def test_batch_autotuner_tunes_each_shape_on_its_batch(gpu_lib):
     q = [_dict(synth.make_problem(64, 64, 910 + i), "f64") for i in range(2)]
     r64 = gpu_lib.autotune_batch(c64, q, sweeps=4)
     assert list(r64) == [(64, 64)] and r64[(64, 64)][0] == 1 and list(r64[(64, 64)][1]) == [1]
+
+
+def test_batch_autotuner_error_keeps_tilings(gpu_lib):
+    """A map whose data hold a NaN on an observed pixel: wf_autotune_batch
+    returns the solve's error (WF_ENONFINITE) and the group's contexts keep
+    the tiling they had."""
+    import torch
+    probs = [synth.make_problem(256, 256, 920 + i) for i in range(2)]
+    pbs = [_dict(p, "f32") for p in probs]
+    pbs[1]["d"][7, 9] = float("nan")
+    ctxs = [gpu_lib.Context(256, 256, "f32") for _ in probs]
+    for c in ctxs:
+        assert c.set_tile(6)
+    with pytest.raises(gpu_lib.WFError) as e:
+        gpu_lib.autotune_batch(ctxs, pbs, sweeps=4)
+    assert e.value.status == -3
+    assert all(c.tile == 6 for c in ctxs)
+    torch.cuda.synchronize()
