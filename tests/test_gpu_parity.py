@@ -283,6 +283,18 @@ def test_full_size_parity_float32_1024(gpu_lib):
     _assert_parity(s_gpu, res.s, "f32")
 
 
+@pytest.mark.parametrize("shape", [(4096, 128), (128, 4096)])
+def test_parity_float32_4096_point_kernels(gpu_lib, shape):
+    """The float32 kernels at the longest supported length: 4096-point
+    column transforms (16 values per thread, per-mode state four modes at a
+    time) and 4096-point row transforms, masked three-level chain."""
+    ny, nx = shape
+    p = synth.make_problem(ny, nx, 27, mask_frac=0.05)
+    s_gpu, rep, trace, res = _run_both(gpu_lib, p, "f32", _ramp(8, 12), monitor_every=4)
+    assert rep["sweeps"] == 12
+    _assert_parity(s_gpu, res.s, "f32")
+
+
 @pytest.mark.parametrize("prec,n,tile", [("f32", 1536, 1), ("f32", 1536, 5), ("f32", 768, 3),
                                          ("f64", 1536, 1)])
 def test_full_size_parity_radix3(gpu_lib, prec, n, tile):
