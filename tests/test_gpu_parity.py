@@ -283,14 +283,16 @@ def test_full_size_parity_float32_1024(gpu_lib):
     _assert_parity(s_gpu, res.s, "f32")
 
 
+@pytest.mark.parametrize("chain", ["three", "merged", "augmented"])
 @pytest.mark.parametrize("shape", [(4096, 128), (128, 4096)])
-def test_parity_float32_4096_point_kernels(gpu_lib, shape):
+def test_parity_float32_4096_point_kernels(gpu_lib, shape, chain):
     """The float32 kernels at the longest supported length: 4096-point
     column transforms (16 values per thread, per-mode state four modes at a
-    time) and 4096-point row transforms, masked three-level chain."""
+    time) and 4096-point row transforms, masked, every chain."""
     ny, nx = shape
     p = synth.make_problem(ny, nx, 27, mask_frac=0.05)
-    s_gpu, rep, trace, res = _run_both(gpu_lib, p, "f32", _ramp(8, 12), monitor_every=4)
+    s_gpu, rep, trace, res = _run_both(gpu_lib, p, "f32", _ramp(8, 12), monitor_every=4,
+                                       chain=chain)
     assert rep["sweeps"] == 12
     _assert_parity(s_gpu, res.s, "f32")
 
